@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs for the DPP sampler: marginal kernels and uniform streams.
+
+This module only builds inputs. It holds none of the sampler's arithmetic and is
+shared by the tests, the smoke check and the benchmark (both the GPU path and the
+CPU oracle receive exactly the bytes it produces).
+
+Kernels follow the admissibility facts the paper relies on: a Hermitian matrix
+is a marginal kernel iff its eigenvalues lie in [0, 1] (Macchi, Sec. 1), a
+diagonal similarity of a kernel defines the same DPP (Prop. 2), and an
+orthogonal projection of rank k gives samples of size exactly k (Sec. 1).
+
+Random numbers come from numpy's PCG64 (``default_rng(seed)``).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform_stream(n: int, seed: int) -> np.ndarray:
+    """u_j ~ U[0, 1), FP64, one per index."""
+    return np.random.default_rng(seed).random(n)
+
+
+def symmetrize_lower(K: np.ndarray) -> np.ndarray:
+    """Copy the lower triangle onto the upper one, so K is exactly symmetric."""
+    return np.tril(K) + np.tril(K, -1).T
+
+
+def _orthonormal(rng, rows: int, cols: int) -> np.ndarray:
+    """Q factor of the Householder QR of a seeded N(0,1) rows x cols matrix."""
+    G = rng.standard_normal((rows, cols))
+    Q, _ = np.linalg.qr(G, mode="reduced")
+    return Q
+
+
+def hermitian_kernel(n: int, seed: int) -> np.ndarray:
+    """K = Q diag(lam) Q^T with Q from QR of N(0,1) n x n and lam_i ~ U(0,1)."""
+    rng = np.random.default_rng(seed)
+    Q = _orthonormal(rng, n, n)
+    lam = rng.random(n)
+    return np.asfortranarray(symmetrize_lower((Q * lam) @ Q.T))
+
+
+def projection_kernel(n: int, rank: int, seed: int, device=None):
+    """K = Q_r Q_r^T with Q_r the Q factor of QR of a seeded N(0,1) n x rank matrix.
+
+    With ``device`` (a torch CUDA device) the QR and the product run on that
+    device (FP64) and a device tensor is returned (column-major storage, i.e.
+    the transpose view of a row-major buffer; K is symmetric so the bytes are
+    the same). The Gaussian matrix is always drawn on the host from the seed.
+    """
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, rank))
+    if device is None:
+        Q, _ = np.linalg.qr(G, mode="reduced")
+        return np.asfortranarray(symmetrize_lower(Q @ Q.T))
+    import torch
+    Gd = torch.from_numpy(G).to(device)
+    Q, _ = torch.linalg.qr(Gd, mode="reduced")
+    del Gd
+    K = Q @ Q.T
+    del Q
+    K = torch.tril(K) + torch.tril(K, -1).T
+    return K.contiguous()
+
+
+def similarity_kernel(n: int, seed: int):
+    """Non-Hermitian kernel of the same DPP as a Hermitian one (Prop. 2).
+
+    H = Q diag(lam) Q^T with lam_i ~ Beta(0.5, 2); s_i = exp(z_i), z_i ~ N(0, 0.5)
+    (standard deviation 0.5); K = S H S^{-1}, i.e. K_ij = s_i H_ij / s_j.
+    Returns (K, H).
+    """
+    rng = np.random.default_rng(seed)
+    Q = _orthonormal(rng, n, n)
+    lam = rng.beta(0.5, 2.0, size=n)
+    H = symmetrize_lower((Q * lam) @ Q.T)
+    z = rng.normal(0.0, 0.5, size=n)
+    s = np.exp(z)
+    K = (s[:, None] * H) / s[None, :]
+    return np.asfortranarray(K), np.asfortranarray(H)
+
+
+def lensemble_kernel(n: int, seed: int, rank: int = 64, dtype=np.float32) -> np.ndarray:
+    """Marginal kernel of a rank-`rank` L-ensemble, formed in FP64, stored in `dtype`.
+
+    Phi ~ N(0, 1/rank) (variance 1/rank), q_i ~ LogNormal(0, 0.5),
+    F = diag(q) Phi, L = F F^T and K = L (L + I)^{-1} = F (I + F^T F)^{-1} F^T.
+    """
+    rng = np.random.default_rng(seed)
+    Phi = rng.normal(0.0, 1.0 / np.sqrt(rank), size=(n, rank))
+    q = rng.lognormal(0.0, 0.5, size=n)
+    F = q[:, None] * Phi
+    M = np.eye(rank) + F.T @ F
+    K = F @ np.linalg.solve(M, F.T)
+    return np.asfortranarray(symmetrize_lower(K).astype(dtype))
+
+
+def lensemble_batch_sizes(count: int, seed: int, lo: int = 64, hi: int = 1024) -> np.ndarray:
+    """n_i ~ U{lo..hi} (inclusive) for a batch of L-ensemble kernels."""
+    return np.random.default_rng(seed).integers(lo, hi + 1, size=count)
+
+
+def grid_transfer_current_kernel(d: int):
+    """Transfer-current kernel of the d x d vertex grid graph of Z^2.
+
+    Its DPP is the uniform distribution over spanning trees (the paper's 40 x 40
+    example, Sec. 1): K = B^T (B B^T)^{-1} B with B the vertex-edge incidence
+    matrix with one vertex row removed. Edges are ordered horizontal then
+    vertical. Returns (K, edges) with edges an (E, 2) array of vertex ids.
+    """
+    edges = []
+    for y in range(d):
+        for x in range(d - 1):
+            edges.append((y * d + x, y * d + x + 1))
+    for y in range(d - 1):
+        for x in range(d):
+            edges.append((y * d + x, (y + 1) * d + x))
+    edges = np.asarray(edges, dtype=np.int64)
+    V, E = d * d, len(edges)
+    B = np.zeros((V, E))
+    B[edges[:, 0], np.arange(E)] = 1.0
+    B[edges[:, 1], np.arange(E)] = -1.0
+    Br = B[1:, :]
+    K = Br.T @ np.linalg.solve(Br @ Br.T, Br)
+    return np.asfortranarray(symmetrize_lower(K)), edges
