@@ -1,0 +1,175 @@
+/*
+ * dpp.h - C ABI of the MI355X (gfx950) factorization-based DPP sampler.
+ *
+ * The library samples a finite Determinantal Point Process from its marginal
+ * kernel K (Poulson, "High-performance sampling of generic Determinantal Point
+ * Processes", Sec. 2 Theorem 2 and Sec. 3, blocked sampler) by running an
+ * unpivoted right-looking factorization of K in which pivot j is modified by a
+ * Bernoulli draw: with d_j the current diagonal entry (the inclusion
+ * probability of j conditioned on the decisions for 0..j-1, Props. 3-5),
+ * index j is kept iff u_j < d_j, otherwise d_j is replaced by d_j - 1; the
+ * column is then scaled by the modified pivot and the trailing Schur
+ * complement is updated. Hermitian (real symmetric) K uses the LDL^H
+ * specialization, general K the LU form.
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer argument except `probs` of the batched calls and the
+ *     return-value strings is a DEVICE pointer owned by the caller. The library
+ *     allocates no memory: all scratch space comes from the caller's workspace
+ *     `ws` of `ws_bytes` bytes (query the size with dpp_workspace_size*).
+ *   - Matrices are column-major with leading dimension lda >= max(1, n).
+ *   - `stream` is a hipStream_t (NULL: the default stream). Calls are
+ *     asynchronous: outputs are valid once the stream has reached the end of
+ *     the call. The library issues one fixed launch sequence per call whose
+ *     shape depends only on (n, dtype, precision), never on the decisions.
+ *   - Argument errors (n < 1, lda < n, NULL pointers, workspace too small,
+ *     unknown enum values) are returned synchronously and nothing is launched.
+ *   - Numerical trouble never returns an error code; it is reported in `info`
+ *     (LAPACK style, see below).
+ *   - Calls on one stream are ordered. Two calls that share a workspace or an
+ *     output buffer must not run concurrently on different streams.
+ */
+#ifndef DPP_H
+#define DPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DPP_OK = 0,
+    DPP_ERR_INVALID_ARG = 1, /* bad size, stride, pointer or enum value          */
+    DPP_ERR_WORKSPACE = 2,   /* ws is NULL or ws_bytes below the required size     */
+    DPP_ERR_HIP = 3,         /* a HIP runtime call (launch, copy) failed           */
+    DPP_ERR_UNSUPPORTED = 4  /* no gfx950 device, or an unsupported combination    */
+} dpp_status;
+
+/* Storage type of A. The pivots, the keep/reject test and the log-likelihood
+   are always computed in FP64; with DPP_F32 the Schur complements are rounded
+   to FP32 when they are stored back. */
+typedef enum { DPP_F64 = 0, DPP_F32 = 1 } dpp_dtype;
+
+/* Arithmetic of the Schur-complement (trailing) updates.
+   DPP_PREC_FP64: FP64 MFMA products, FP64 accumulation.
+   DPP_PREC_SPLIT_BF16: each factor x is split as x = hi + lo with hi = bf16(x)
+   and lo = bf16(x - hi); the update is hi*hi' + hi*lo' + lo*hi' on BF16 MFMA
+   with FP32 accumulation, subtracted from the stored value in the storage
+   precision. The diagonal-block decisions, the panel solves and the
+   log-likelihood stay in FP64 on both paths. */
+typedef enum { DPP_PREC_FP64 = 0, DPP_PREC_SPLIT_BF16 = 1 } dpp_precision;
+
+/*
+ * dpp_sample_ldlh - sample DPP(K) for Hermitian (real symmetric) K.
+ *
+ *   A       in/out, n x n, dtype dt. Only the LOWER triangle is read and written.
+ *           On entry the lower triangle of K. On exit the strict lower triangle
+ *           holds the unit-lower L and the diagonal holds D of
+ *           K - 1_{Y^c} = L D L^T (the in-place factorization named in the
+ *           caption of the paper's unblocked listing), with 1_{Y^c} the
+ *           diagonal indicator of the rejected indices.
+ *   u       in, n FP64 uniforms; u_j is consumed for index j. Values in [0,1)
+ *           are the intended use; u_j = 1 forces a rejection.
+ *   mask    out, n bytes: 1 if index j is in the sample, else 0.
+ *   pivots  out, n FP64: d'_j, the pivot after the decision (d_j if kept,
+ *           d_j - 1 if rejected), so the pre-decision probability is
+ *           pivots[j] + 1 - mask[j].
+ *   loglik  out, 1 FP64: sum_j ln|d'_j|, the natural log of the likelihood of
+ *           the returned sample (Theorem 2), summed in a fixed order (the
+ *           result is bitwise reproducible).
+ *   info    out, 1 int32: 0, or j+1 for the first j whose pivot d'_j is exactly
+ *           zero or NaN. Then loglik is -inf or NaN and the outputs for indices
+ *           after j are unspecified.
+ *   prec    trailing-update arithmetic (see dpp_precision).
+ *   ws      device workspace of at least dpp_workspace_size(1, dt, n, prec)
+ *           bytes; its contents on entry are ignored.
+ */
+dpp_status dpp_sample_ldlh(void* A, dpp_dtype dt, int64_t n, int64_t lda, const double* u,
+                           uint8_t* mask, double* pivots, double* loglik, int32_t* info,
+                           dpp_precision prec, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * dpp_sample_lu - sample DPP(K) for general (non-Hermitian) K, the unpivoted LU
+ * form of the sampler (Sec. 2 listing, Sec. 3 blocked LU listing).
+ *   A   in/out, all n x n entries. On exit the strict lower triangle holds the
+ *       unit-lower L and the upper triangle (with the diagonal) holds U of
+ *       K - 1_{Y^c} = L U.
+ * The other arguments are as for dpp_sample_ldlh;
+ * ws needs dpp_workspace_size(0, dt, n, prec) bytes.
+ */
+dpp_status dpp_sample_lu(void* A, dpp_dtype dt, int64_t n, int64_t lda, const double* u,
+                         uint8_t* mask, double* pivots, double* loglik, int32_t* info,
+                         dpp_precision prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for one problem. hermitian: 1 for dpp_sample_ldlh, 0 for
+   dpp_sample_lu. Returns 0 for invalid arguments. */
+size_t dpp_workspace_size(int hermitian, dpp_dtype dt, int64_t n, dpp_precision prec);
+
+/* One problem of a batched call. All pointers are device pointers; the fields
+   mean what the arguments of the same names mean for the single calls. */
+typedef struct {
+    void* A;
+    int64_t n;
+    int64_t lda;
+    const double* u;
+    uint8_t* mask;
+    double* pivots;
+    double* loglik;
+    int32_t* info;
+} dpp_problem;
+
+/*
+ * dpp_sample_ldlh_batched / dpp_sample_lu_batched - `count` independent
+ * problems, each with its own n, lda, stream of uniforms and outputs, sampled
+ * by one launch sequence on `stream` (each step of the factorization is one
+ * launch covering every problem that still has that step).
+ *   probs   HOST array of `count` descriptors; it is read before the call
+ *           returns and may be reused at once.
+ *   ws      device workspace of dpp_workspace_size_batched(...) bytes.
+ * Every problem's results equal those of the single call on that problem
+ * (bit for bit): the blocking depends only on (dtype, precision), and the
+ * problems do not interact. Problems must not share A or output buffers.
+ */
+dpp_status dpp_sample_ldlh_batched(const dpp_problem* probs, int64_t count, dpp_dtype dt,
+                                   dpp_precision prec, void* ws, size_t ws_bytes, void* stream);
+dpp_status dpp_sample_lu_batched(const dpp_problem* probs, int64_t count, dpp_dtype dt,
+                                 dpp_precision prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for a batch whose problem sizes are ns[0..count-1] (host
+   array). Returns 0 for invalid arguments. */
+size_t dpp_workspace_size_batched(int hermitian, dpp_dtype dt, const int64_t* ns, int64_t count,
+                                  dpp_precision prec);
+
+/* Static, NUL-terminated description of a status code. */
+const char* dpp_status_string(dpp_status s);
+
+/*
+ * Profiling of the library's own kernel launches (process-wide).
+ * dpp_profile_begin() clears previous records and starts recording: every
+ * subsequent launch of the library is bracketed by two hipEvents on its
+ * stream, and its algorithmic work is noted (flops of the Schur updates with
+ * the n^3/3 (LDL^H) / 2n^3/3 (LU) convention's per-element count, and the
+ * minimum HBM bytes the launch must move). dpp_profile_end() waits for the
+ * recorded events, fills up to `max` entries of `out` (one per kernel that
+ * ran), stops recording and returns the number of entries (negative on a HIP
+ * error). Recording adds two event records per launch; do not profile calls
+ * from several host threads at once.
+ */
+typedef struct {
+    char name[32];     /* kernel family, e.g. "update_bf16x3"            */
+    int64_t launches;  /* launches recorded                               */
+    double ms;         /* sum of event-measured durations (milliseconds) */
+    double flops;      /* algorithmic flops of those launches            */
+    double bytes;      /* algorithmic HBM bytes of those launches        */
+} dpp_kernel_stats;
+
+int dpp_profile_begin(void);
+int dpp_profile_end(dpp_kernel_stats* out, int max);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPP_H */

@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libdpp.so (include/dpp.h). Argument marshalling only:
+every step of the sampler runs in the library's HIP kernels.
+
+Functions carry the C names. Matrices are torch CUDA tensors in column-major
+layout (stride(0) == 1, stride(1) == lda >= n); `colmajor()` makes one.
+Outputs are torch tensors allocated here when not given. Calls are issued on
+torch's current stream of the tensor's device and are asynchronous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpp.so")
+
+DPP_F64, DPP_F32 = 0, 1
+DPP_PREC_FP64, DPP_PREC_SPLIT_BF16 = 0, 1
+DPP_OK = 0
+_STATUS = {0: "DPP_OK", 1: "DPP_ERR_INVALID_ARG", 2: "DPP_ERR_WORKSPACE", 3: "DPP_ERR_HIP",
+           4: "DPP_ERR_UNSUPPORTED"}
+
+_vp, _i64 = ctypes.c_void_p, ctypes.c_int64
+
+
+class DppError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_STATUS.get(status, status)} ({dpp_status_string(status)})")
+
+
+class dpp_problem(ctypes.Structure):
+    _fields_ = [("A", _vp), ("n", _i64), ("lda", _i64), ("u", _vp), ("mask", _vp),
+                ("pivots", _vp), ("loglik", _vp), ("info", _vp)]
+
+
+class dpp_kernel_stats(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", _i64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libdpp.so. Fails loudly when it has not been built: there is no
+    other implementation to fall back to."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(or python -m paper_1905_00165_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    single = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp,
+              ctypes.c_size_t, _vp]
+    for name in ("dpp_sample_ldlh", "dpp_sample_lu"):
+        f = getattr(L, name)
+        f.argtypes, f.restype = single, ctypes.c_int
+    for name in ("dpp_sample_ldlh_batched", "dpp_sample_lu_batched"):
+        f = getattr(L, name)
+        f.argtypes = [ctypes.POINTER(dpp_problem), _i64, ctypes.c_int, ctypes.c_int, _vp,
+                      ctypes.c_size_t, _vp]
+        f.restype = ctypes.c_int
+    L.dpp_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int]
+    L.dpp_workspace_size.restype = ctypes.c_size_t
+    L.dpp_workspace_size_batched.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64),
+                                             _i64, ctypes.c_int]
+    L.dpp_workspace_size_batched.restype = ctypes.c_size_t
+    L.dpp_status_string.argtypes = [ctypes.c_int]
+    L.dpp_status_string.restype = ctypes.c_char_p
+    L.dpp_profile_begin.argtypes = []
+    L.dpp_profile_begin.restype = ctypes.c_int
+    L.dpp_profile_end.argtypes = [ctypes.POINTER(dpp_kernel_stats), ctypes.c_int]
+    L.dpp_profile_end.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def dpp_status_string(status: int) -> str:
+    return lib().dpp_status_string(int(status)).decode()
+
+
+def dpp_workspace_size(hermitian: bool, dtype: int, n: int, prec: int) -> int:
+    return int(lib().dpp_workspace_size(int(bool(hermitian)), int(dtype), int(n), int(prec)))
+
+
+def dpp_workspace_size_batched(hermitian: bool, dtype: int, ns, prec: int) -> int:
+    arr = (_i64 * len(ns))(*[int(x) for x in ns])
+    return int(lib().dpp_workspace_size_batched(int(bool(hermitian)), int(dtype), arr, len(ns),
+                                                int(prec)))
+
+
+def dpp_profile_begin() -> None:
+    """Start recording the library's launches (hipEvents around each)."""
+    lib().dpp_profile_begin()
+
+
+def dpp_profile_end() -> dict:
+    """Stop recording; {kernel: {launches, ms, flops, bytes}} of what ran."""
+    buf = (dpp_kernel_stats * 16)()
+    k = lib().dpp_profile_end(buf, 16)
+    if k < 0:
+        raise DppError(3, "dpp_profile_end")
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms,
+                                   "flops": buf[i].flops, "bytes": buf[i].bytes}
+            for i in range(k)}
+
+
+# ----------------------------------------------------------------- torch glue
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(K, device=None, dtype=None):
+    """A column-major (stride(0) == 1) copy of matrix K on `device`."""
+    torch = _torch()
+    t = torch.as_tensor(K)
+    if dtype is not None:
+        t = t.to(dtype)
+    if device is not None:
+        t = t.to(device)
+    return t.t().contiguous().t()
+
+
+def _dtype_code(A) -> int:
+    torch = _torch()
+    if A.dtype == torch.float64:
+        return DPP_F64
+    if A.dtype == torch.float32:
+        return DPP_F32
+    raise TypeError(f"A must be float64 or float32, got {A.dtype}")
+
+
+def _check_matrix(A):
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square 2-D tensor")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    n = A.shape[0]
+    if n > 1 and A.stride(0) != 1:
+        raise ValueError("A must be column-major (stride(0) == 1); use colmajor()")
+    lda = A.stride(1) if n > 1 else max(1, A.stride(1))
+    return n, lda
+
+
+def _outputs(n, device, out):
+    torch = _torch()
+    if out is None:
+        out = {}
+    o = dict(out)
+    o.setdefault("mask", torch.empty(n, dtype=torch.uint8, device=device))
+    o.setdefault("pivots", torch.empty(n, dtype=torch.float64, device=device))
+    o.setdefault("loglik", torch.empty(1, dtype=torch.float64, device=device))
+    o.setdefault("info", torch.empty(1, dtype=torch.int32, device=device))
+    return o
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _single(name, hermitian, A, u, prec, ws, out):
+    torch = _torch()
+    n, lda = _check_matrix(A)
+    dt = _dtype_code(A)
+    if u.dtype != torch.float64 or u.device != A.device or u.numel() < n or not u.is_contiguous():
+        raise ValueError("u must be a contiguous float64 device tensor with >= n entries")
+    need = dpp_workspace_size(hermitian, dt, n, prec)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    o = _outputs(n, A.device, out)
+    st = getattr(lib(), name)(A.data_ptr(), dt, n, lda, u.data_ptr(), o["mask"].data_ptr(),
+                              o["pivots"].data_ptr(), o["loglik"].data_ptr(),
+                              o["info"].data_ptr(), int(prec), ws.data_ptr(), ws.numel(),
+                              _stream_handle(A.device))
+    if st != DPP_OK:
+        raise DppError(st, name)
+    return o
+
+
+def dpp_sample_ldlh(A, u, prec=DPP_PREC_FP64, ws=None, out=None):
+    """Sample DPP(K) for symmetric K given in the lower triangle of the
+    column-major device tensor A (overwritten by L and D of K - 1_{Y^c}).
+    Returns a dict of device tensors: mask, pivots, loglik, info."""
+    return _single("dpp_sample_ldlh", True, A, u, prec, ws, out)
+
+
+def dpp_sample_lu(A, u, prec=DPP_PREC_FP64, ws=None, out=None):
+    """Sample DPP(K) for general K (all of A; overwritten by L and U)."""
+    return _single("dpp_sample_lu", False, A, u, prec, ws, out)
+
+
+def _batched(name, hermitian, As, us, prec, ws, outs):
+    torch = _torch()
+    if len(As) != len(us) or not As:
+        raise ValueError("need matching, non-empty lists of matrices and streams")
+    dt = _dtype_code(As[0])
+    probs = (dpp_problem * len(As))()
+    res = []
+    ns = []
+    for i, (A, u) in enumerate(zip(As, us)):
+        n, lda = _check_matrix(A)
+        if _dtype_code(A) != dt:
+            raise ValueError("all matrices of a batch share one dtype")
+        if u.dtype != torch.float64 or u.numel() < n or not u.is_contiguous():
+            raise ValueError("each u must be a contiguous float64 device tensor with >= n entries")
+        o = _outputs(n, A.device, outs[i] if outs else None)
+        probs[i] = dpp_problem(A.data_ptr(), n, lda, u.data_ptr(), o["mask"].data_ptr(),
+                               o["pivots"].data_ptr(), o["loglik"].data_ptr(),
+                               o["info"].data_ptr())
+        res.append(o)
+        ns.append(n)
+    need = dpp_workspace_size_batched(hermitian, dt, ns, prec)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=As[0].device)
+    st = getattr(lib(), name)(probs, len(As), dt, int(prec), ws.data_ptr(), ws.numel(),
+                              _stream_handle(As[0].device))
+    if st != DPP_OK:
+        raise DppError(st, name)
+    return res
+
+
+def dpp_sample_ldlh_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None):
+    """Independent symmetric problems in one launch sequence."""
+    return _batched("dpp_sample_ldlh_batched", True, As, us, prec, ws, outs)
+
+
+def dpp_sample_lu_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None):
+    """Independent general problems in one launch sequence."""
+    return _batched("dpp_sample_lu_batched", False, As, us, prec, ws, outs)

@@ -1,0 +1,414 @@
+// Host side of the C ABI declared in include/dpp.h: argument checks, workspace
+// layout and the fixed launch sequence of the blocked sampler.
+//
+// Launch sequence (blocked right-looking sampler, Sec. 3; the unblocked
+// sampler of Sec. 2 on each 64-wide diagonal block):
+//
+//   LDL^H, outer block width B0 (FP64: 256, split-BF16: 512):
+//     for each outer panel [j0, j1):
+//       factor_panel(j0, j1)                       -- recursive, below
+//       update rows/cols [j1, n) by columns [j0, j1) -- the trailing update
+//     factor_panel(c0, c1): width <= 64 -> one diagonal-block launch; else
+//       split at mid (a multiple of 64), factor_panel(c0, mid),
+//       update rows [mid, n) x cols [mid, c1) by columns [c0, mid),
+//       factor_panel(mid, c1).
+//   LU: one level, B0 = 64: diagonal block + both panel solves, then the
+//     trailing update by those 64 columns.
+//   Then one finalize launch (loglik, info).
+//
+// Every grouping of the Schur updates is exact in exact arithmetic: the -1 of
+// a rejected pivot commutes with the outer-product updates (Prop. 5). The
+// sequence depends only on (n, dtype, precision), never on the decisions, so
+// there is no device-to-host traffic inside a call.
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "dpp.h"
+#include "dpp_internal.h"
+
+namespace {
+
+using dpp::DevProb;
+using dpp::kLeaf;
+
+struct Plan {
+    bool herm;
+    int dtype;   // 0 FP64 storage, 1 FP32 storage
+    bool split;  // split-BF16 updates
+    int B0;      // outer panel width (multiple of kLeaf)
+    int ss;      // row stride of the split panel copies (elements), >= B0
+};
+
+Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec)
+{
+    Plan p;
+    p.herm = herm;
+    p.dtype = (dt == DPP_F32) ? 1 : 0;
+    p.split = (prec == DPP_PREC_SPLIT_BF16);
+    if (herm) p.B0 = p.split ? 512 : 256;
+    else p.B0 = kLeaf;
+    p.ss = p.B0;
+    return p;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+size_t split_bytes(const Plan& p, int64_t n)
+{
+    return p.split ? align_up((size_t)4 * (size_t)n * (size_t)p.ss * sizeof(uint16_t)) : 0;
+}
+// Workspace layout: [descriptors][sink, kAlign bytes][split copies per problem].
+size_t desc_bytes(int64_t count) { return align_up((size_t)count * sizeof(DevProb)) + kAlign; }
+
+bool valid_enums(dpp_dtype dt, dpp_precision prec)
+{
+    return (dt == DPP_F64 || dt == DPP_F32) &&
+           (prec == DPP_PREC_FP64 || prec == DPP_PREC_SPLIT_BF16);
+}
+
+// gfx950 check, cached per device ordinal.
+dpp_status device_ok()
+{
+    static std::mutex mu;
+    static std::vector<int> state;  // 0 unknown, 1 ok, 2 unsupported
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DPP_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)state.size() <= dev) state.resize(dev + 1, 0);
+    if (state[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DPP_ERR_UNSUPPORTED;
+        state[dev] = (strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 2;
+    }
+    return state[dev] == 1 ? DPP_OK : DPP_ERR_UNSUPPORTED;
+}
+
+// ------------------------------------------------------------------ profiling
+// Kernel families whose launches the profiler tells apart.
+enum KernelId { K_LEAF_LDLH, K_LEAF_LU, K_UPDATE_F64, K_UPDATE_BF16X3, K_FINALIZE, K_DESCS, K_COUNT };
+const char* const kKernelNames[K_COUNT] = {"leaf_ldlh", "leaf_lu", "update_f64", "update_bf16x3",
+                                           "finalize", "store_descs"};
+
+struct ProfRecord {
+    int id;
+    hipEvent_t ev0, ev1;
+    double flops, bytes;
+};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;  // created once, reused
+    size_t used = 0;
+    std::vector<ProfRecord> recs;
+
+    hipEvent_t take()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+};
+Profiler& prof()
+{
+    static Profiler p;
+    return p;
+}
+
+struct Ctx {
+    Plan plan;
+    const DevProb* probs;  // device
+    int count;
+    int64_t nmax;
+    hipStream_t s;
+    const std::vector<int64_t>* ns;  // host copy of the problem sizes
+    bool profiling;
+};
+
+#define DPP_TRY(expr)                                  \
+    do {                                               \
+        if ((expr) != hipSuccess) return DPP_ERR_HIP;  \
+    } while (0)
+
+// Runs `launch` (returning hipError_t); with profiling on, brackets it with
+// events and notes its algorithmic work.
+template <typename F>
+dpp_status timed(const Ctx& c, int id, double flops, double bytes, F&& launch)
+{
+    if (!c.profiling) {
+        DPP_TRY(launch());
+        return DPP_OK;
+    }
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    ProfRecord r{id, p.take(), p.take(), flops, bytes};
+    if (!r.ev0 || !r.ev1) return DPP_ERR_HIP;
+    DPP_TRY(hipEventRecord(r.ev0, c.s));
+    DPP_TRY(launch());
+    DPP_TRY(hipEventRecord(r.ev1, c.s));
+    p.recs.push_back(r);
+    return DPP_OK;
+}
+
+// Algorithmic work of a Schur update of rows [base, n) x cols [base, base+ncols)
+// by kw factored columns, summed over the problems that have it.
+void update_work(const Ctx& c, int64_t base, int64_t ncols, int kw, double& flops, double& bytes)
+{
+    flops = bytes = 0.0;
+    const double elt = c.plan.dtype == 0 ? 8.0 : 4.0;
+    const double opnd = c.plan.split ? 4.0 : elt;  // hi+lo bf16, or one stored value
+    for (int64_t n : *c.ns) {
+        const int64_t nr = n - base;
+        if (nr <= 0) continue;
+        const int64_t nc = ncols < nr ? ncols : nr;
+        const double e = c.plan.herm ? (double)nc * nr - (double)nc * (nc - 1) / 2.0
+                                     : (double)nr * nc;
+        flops += 2.0 * e * kw;
+        bytes += 2.0 * e * elt + (double)(nr + nc) * kw * opnd;
+    }
+}
+
+void leaf_work(const Ctx& c, int64_t c0, double& flops, double& bytes)
+{
+    flops = bytes = 0.0;
+    const double elt = c.plan.dtype == 0 ? 8.0 : 4.0;
+    const double sides = c.plan.herm ? 1.0 : 2.0;  // LU also solves the row panel
+    for (int64_t n : *c.ns) {
+        if (c0 >= n) continue;
+        const double bs = (double)((n - c0) < kLeaf ? (n - c0) : kLeaf);
+        const double m = (double)(n - c0) - bs;
+        flops += bs * bs * bs / 3.0 * (c.plan.herm ? 1.0 : 2.0) + sides * m * bs * bs;
+        bytes += (bs * bs + 2.0 * sides * m * bs) * elt + (c.plan.split ? sides * m * bs * 8.0 : 0.0);
+    }
+}
+
+dpp_status update(const Ctx& c, int64_t base, int64_t ncols, int64_t k0, int kw, int64_t j0)
+{
+    double fl = 0, by = 0;
+    if (c.profiling) update_work(c, base, ncols, kw, fl, by);
+    if (c.plan.split)
+        return timed(c, K_UPDATE_BF16X3, fl, by, [&] {
+            return dpp::launch_update_bf16x3(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax,
+                                             base, ncols, k0, kw, j0, c.plan.ss, c.s);
+        });
+    return timed(c, K_UPDATE_F64, fl, by, [&] {
+        return dpp::launch_update_f64(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax, base,
+                                      ncols, k0, kw, c.s);
+    });
+}
+
+dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
+{
+    double fl = 0, by = 0;
+    if (c.profiling) leaf_work(c, c0, fl, by);
+    if (c.plan.herm)
+        return timed(c, K_LEAF_LDLH, fl, by, [&] {
+            return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.split, c.probs, c.count, c.nmax, c0,
+                                         j0, c.plan.ss, c.s);
+        });
+    return timed(c, K_LEAF_LU, fl, by, [&] {
+        return dpp::launch_leaf_lu(c.plan.dtype, c.plan.split, c.probs, c.count, c.nmax, c0, j0,
+                                   c.plan.ss, c.s);
+    });
+}
+
+dpp_status factor_panel(const Ctx& c, int64_t c0, int64_t c1, int64_t j0)
+{
+    if (c1 - c0 <= kLeaf) return leaf(c, c0, j0);
+    const int64_t nb = (c1 - c0 + kLeaf - 1) / kLeaf;
+    const int64_t mid = c0 + ((nb + 1) / 2) * kLeaf;
+    dpp_status st = factor_panel(c, c0, mid, j0);
+    if (st != DPP_OK) return st;
+    if (mid < c.nmax) {
+        st = update(c, mid, c1 - mid, c0, (int)(mid - c0), j0);
+        if (st != DPP_OK) return st;
+    }
+    return factor_panel(c, mid, c1, j0);
+}
+
+dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
+               dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!probs || count < 1 || count > 65535 || !valid_enums(dt, prec)) return DPP_ERR_INVALID_ARG;
+    const Plan plan = make_plan(herm, dt, prec);
+    int64_t nmax = 0;
+    size_t need = desc_bytes(count);
+    for (int64_t i = 0; i < count; ++i) {
+        const dpp_problem& q = probs[i];
+        if (q.n < 1 || q.lda < q.n || !q.A || !q.u || !q.mask || !q.pivots || !q.loglik ||
+            !q.info)
+            return DPP_ERR_INVALID_ARG;
+        if (q.n > (int64_t)1 << 31) return DPP_ERR_INVALID_ARG;
+        nmax = q.n > nmax ? q.n : nmax;
+        need += split_bytes(plan, q.n);
+    }
+    if (!ws || ws_bytes < need) return DPP_ERR_WORKSPACE;
+    const dpp_status dev = device_ok();
+    if (dev != DPP_OK) return dev;
+
+    std::vector<DevProb> host((size_t)count);
+    char* cursor = static_cast<char*>(ws) + desc_bytes(count);
+    void* sink = cursor - kAlign;
+    for (int64_t i = 0; i < count; ++i) {
+        const dpp_problem& q = probs[i];
+        DevProb& d = host[(size_t)i];
+        d.A = q.A;
+        d.n = q.n;
+        d.lda = q.lda;
+        d.u = q.u;
+        d.mask = q.mask;
+        d.piv = q.pivots;
+        d.loglik = q.loglik;
+        d.info = q.info;
+        d.split = plan.split ? reinterpret_cast<uint16_t*>(cursor) : nullptr;
+        d.sink = sink;
+        cursor += split_bytes(plan, q.n);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int64_t> ns((size_t)count);
+    for (int64_t i = 0; i < count; ++i) ns[(size_t)i] = probs[i].n;
+    bool profiling;
+    {
+        std::lock_guard<std::mutex> g(prof().mu);
+        profiling = prof().on;
+    }
+    Ctx c{plan, static_cast<const DevProb*>(ws), (int)count, nmax, s, &ns, profiling};
+
+    // Descriptors reach the device as kernel arguments (copied at launch), so
+    // the call neither reads host memory later nor blocks the host.
+    for (int64_t i = 0; i < count; i += dpp::kDescPerLaunch) {
+        const int cnt = (int)((count - i) < dpp::kDescPerLaunch ? (count - i) : dpp::kDescPerLaunch);
+        const dpp_status st = timed(c, K_DESCS, 0.0, 0.0, [&] {
+            return dpp::launch_store_descs(host.data() + i, cnt, static_cast<DevProb*>(ws) + i, s);
+        });
+        if (st != DPP_OK) return st;
+    }
+
+    for (int64_t j0 = 0; j0 < nmax; j0 += plan.B0) {
+        const int64_t j1 = (j0 + plan.B0 < nmax) ? j0 + plan.B0 : nmax;
+        dpp_status st = plan.herm ? factor_panel(c, j0, j1, j0) : leaf(c, j0, j0);
+        if (st != DPP_OK) return st;
+        if (j1 < nmax) {
+            st = update(c, j1, nmax - j1, j0, (int)(j1 - j0), j0);
+            if (st != DPP_OK) return st;
+        }
+    }
+    return timed(c, K_FINALIZE, 0.0, 0.0, [&] { return dpp::launch_finalize(c.probs, c.count, s); });
+}
+
+size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t count,
+                         dpp_precision prec)
+{
+    if (!ns || count < 1 || !valid_enums(dt, prec)) return 0;
+    const Plan plan = make_plan(herm, dt, prec);
+    size_t need = desc_bytes(count);
+    for (int64_t i = 0; i < count; ++i) {
+        if (ns[i] < 1) return 0;
+        need += split_bytes(plan, ns[i]);
+    }
+    return need;
+}
+
+}  // namespace
+
+extern "C" {
+
+dpp_status dpp_sample_ldlh(void* A, dpp_dtype dt, int64_t n, int64_t lda, const double* u,
+                           uint8_t* mask, double* pivots, double* loglik, int32_t* info,
+                           dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
+{
+    const dpp_problem p{A, n, lda, u, mask, pivots, loglik, info};
+    return run(true, &p, 1, dt, prec, ws, ws_bytes, stream);
+}
+
+dpp_status dpp_sample_lu(void* A, dpp_dtype dt, int64_t n, int64_t lda, const double* u,
+                         uint8_t* mask, double* pivots, double* loglik, int32_t* info,
+                         dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
+{
+    const dpp_problem p{A, n, lda, u, mask, pivots, loglik, info};
+    return run(false, &p, 1, dt, prec, ws, ws_bytes, stream);
+}
+
+dpp_status dpp_sample_ldlh_batched(const dpp_problem* probs, int64_t count, dpp_dtype dt,
+                                   dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
+{
+    return run(true, probs, count, dt, prec, ws, ws_bytes, stream);
+}
+
+dpp_status dpp_sample_lu_batched(const dpp_problem* probs, int64_t count, dpp_dtype dt,
+                                 dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
+{
+    return run(false, probs, count, dt, prec, ws, ws_bytes, stream);
+}
+
+size_t dpp_workspace_size(int hermitian, dpp_dtype dt, int64_t n, dpp_precision prec)
+{
+    return workspace_batched(hermitian != 0, dt, &n, 1, prec);
+}
+
+size_t dpp_workspace_size_batched(int hermitian, dpp_dtype dt, const int64_t* ns, int64_t count,
+                                  dpp_precision prec)
+{
+    return workspace_batched(hermitian != 0, dt, ns, count, prec);
+}
+
+int dpp_profile_begin(void)
+{
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.recs.clear();
+    p.used = 0;
+    p.on = true;
+    return 0;
+}
+
+int dpp_profile_end(dpp_kernel_stats* out, int max)
+{
+    Profiler& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.on = false;
+    dpp_kernel_stats acc[K_COUNT];
+    memset(acc, 0, sizeof acc);
+    for (const ProfRecord& r : p.recs) {
+        if (hipEventSynchronize(r.ev1) != hipSuccess) return -1;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.ev0, r.ev1) != hipSuccess) return -1;
+        acc[r.id].launches += 1;
+        acc[r.id].ms += ms;
+        acc[r.id].flops += r.flops;
+        acc[r.id].bytes += r.bytes;
+    }
+    p.recs.clear();
+    p.used = 0;
+    int k = 0;
+    for (int id = 0; id < K_COUNT; ++id) {
+        if (acc[id].launches == 0) continue;
+        if (out && k < max) {
+            out[k] = acc[id];
+            strncpy(out[k].name, kKernelNames[id], sizeof(out[k].name) - 1);
+            out[k].name[sizeof(out[k].name) - 1] = 0;
+        }
+        ++k;
+    }
+    return k < max ? k : max;
+}
+
+const char* dpp_status_string(dpp_status s)
+{
+    switch (s) {
+    case DPP_OK: return "success";
+    case DPP_ERR_INVALID_ARG: return "invalid argument";
+    case DPP_ERR_WORKSPACE: return "workspace missing or too small";
+    case DPP_ERR_HIP: return "HIP runtime error";
+    case DPP_ERR_UNSUPPORTED: return "unsupported device or configuration";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Internal declarations shared by the gfx950 kernels and the host entry points.
+// Not part of the public ABI (include/dpp.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpp {
+
+// Width of the diagonal block whose keep/reject decisions one wavefront makes
+// (one matrix row per lane of the 64-wide wavefront).
+constexpr int kLeaf = 64;
+
+// Per-problem descriptor as the kernels read it (device memory).
+struct DevProb {
+    void* A;          // column-major n x n, lda, storage type T
+    int64_t n;
+    int64_t lda;
+    const double* u;  // n uniforms
+    uint8_t* mask;    // n
+    double* piv;      // n, pivots after the decision
+    double* loglik;   // 1
+    int32_t* info;    // 1
+    uint16_t* split;  // split-BF16 panel copies (see below), or nullptr
+    void* sink;       // 16 bytes of workspace that absorb stores to columns past a
+                      // ragged last block (never read)
+};
+
+// Split-BF16 panel copies of problem p live at split[q * n * ss + r * ss + kk],
+// q = 0: hi(L), 1: lo(L), 2: hi(B), 3: lo(B), r the global row of L (or the
+// global column of the update for B), kk = k - j0 the column of the current
+// outer panel. For LDL^H, B = L D (the scaled column, W); for LU, B = U^T.
+// Values are bf16 bit patterns.
+__host__ __device__ inline uint16_t* split_plane(uint16_t* base, int64_t n, int ss, int q)
+{
+    return base + (int64_t)q * n * ss;
+}
+
+// ------------------------------------------------------------------ launchers
+// Each returns the launch status; `nprob` problems, grid.y indexes problems.
+// nmax is the largest n in the batch; the kernels clamp per problem.
+
+// Diagonal block [c0, c0+64) of every problem: decisions, L11/D1 (or L11/U11),
+// and the panel solves for the rows below it (LU: and the columns to its
+// right). With split != 0 also writes the split-BF16 panel copies at outer
+// panel offset j0 with row stride ss.
+hipError_t launch_leaf_ldlh(int dtype, bool split, const DevProb* probs, int nprob, int64_t nmax,
+                            int64_t c0, int64_t j0, int ss, hipStream_t s);
+hipError_t launch_leaf_lu(int dtype, bool split, const DevProb* probs, int nprob, int64_t nmax,
+                          int64_t c0, int64_t j0, int ss, hipStream_t s);
+
+// Schur-complement update of rows [base, n) x cols [base, min(base+ncols, n))
+// by the K range [k0, k0+kw) of the factored columns; herm: lower part only.
+hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
+                             int64_t base, int64_t ncols, int64_t k0, int kw, hipStream_t s);
+hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int nprob,
+                                int64_t nmax, int64_t base, int64_t ncols, int64_t k0, int kw,
+                                int64_t j0, int ss, hipStream_t s);
+
+// loglik (fixed-order sum of ln|piv|) and info, one workgroup per problem.
+hipError_t launch_finalize(const DevProb* probs, int nprob, hipStream_t s);
+
+// Copy `cnt` (<= kDescPerLaunch) host descriptors to dst through the kernel
+// argument block of a one-workgroup launch.
+constexpr int kDescPerLaunch = 48;
+hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStream_t s);
+
+}  // namespace dpp

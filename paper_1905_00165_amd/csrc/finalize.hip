@@ -1,0 +1,76 @@
+// Log-likelihood and info word of each problem (gfx950).
+//
+// The likelihood of the returned sample is the product of the absolute values
+// of the modified pivots (Theorem 2), so loglik = sum_j ln|d'_j|. The sum runs
+// in a fixed order (each thread sums a contiguous chunk in index order, then a
+// fixed binary tree), so the result is bitwise reproducible. info is the
+// 1-based index of the first pivot that is exactly zero or NaN (0 if none).
+#include "dpp_internal.h"
+
+namespace dpp {
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void finalize(const DevProb* __restrict__ probs)
+{
+    const DevProb P = probs[blockIdx.x];
+    const int64_t n = P.n;
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n + kThreads - 1) / kThreads;
+    const int64_t lo = tid * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    double s = 0.0;
+    int64_t first = INT64_MAX;
+    for (int64_t j = lo; j < hi; ++j) {
+        const double p = P.piv[j];
+        s += log(fabs(p));
+        if (first == INT64_MAX && (p == 0.0 || p != p)) first = j;
+    }
+    __shared__ double ss[kThreads];
+    __shared__ int64_t sf[kThreads];
+    ss[tid] = s;
+    sf[tid] = first;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            ss[tid] = ss[tid] + ss[tid + w];
+            sf[tid] = sf[tid] < sf[tid + w] ? sf[tid] : sf[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        *P.loglik = ss[0];
+        *P.info = sf[0] == INT64_MAX ? 0 : (int32_t)(sf[0] + 1);
+    }
+}
+
+struct DescChunk {
+    DevProb d[kDescPerLaunch];
+    int cnt;
+};
+
+__global__ void store_descs(DescChunk chunk, DevProb* __restrict__ dst)
+{
+    const int i = threadIdx.x;
+    if (i < chunk.cnt) dst[i] = chunk.d[i];
+}
+
+}  // namespace
+
+hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStream_t s)
+{
+    DescChunk chunk;
+    for (int i = 0; i < cnt; ++i) chunk.d[i] = host[i];
+    chunk.cnt = cnt;
+    hipLaunchKernelGGL(store_descs, dim3(1), dim3(64), 0, s, chunk, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevProb* probs, int nprob, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize, dim3(nprob), dim3(kThreads), 0, s, probs);
+    return hipGetLastError();
+}
+
+}  // namespace dpp

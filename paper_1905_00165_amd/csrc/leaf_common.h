@@ -1,0 +1,95 @@
+// Diagonal-block kernels of the blocked DPP sampler (gfx950).
+//
+// One launch handles the 64-wide diagonal block [c0, c0+64) of every problem in
+// a batch. Following the blocked sampler of Sec. 3 (the blocked LU listing with
+// its diagonal-block factorization replaced by the unblocked sampler), each
+// workgroup
+//   1. runs the unblocked sampler (Sec. 2, Theorem 2) on the diagonal block:
+//      at pivot j, with d the current diagonal entry, keep j iff u_j < d, else
+//      d <- d - 1; scale column j by the modified pivot and apply the rank-one
+//      Schur update to the rest of the block. This chain runs on wavefront 0
+//      with one row of the block per lane, held in registers; the column that
+//      drives each rank-one update is broadcast through LDS.
+//   2. solves its share of the panel below the block against the factored
+//      block (and, for LU, of the row panel to its right), one row (column)
+//      per thread with the factored block in LDS.
+// Every workgroup of a launch makes the same decisions from the same data
+// (the chain is deterministic), so the panel solves need no second launch;
+// workgroup 0 alone writes the block, the mask and the pivots.
+// All arithmetic is FP64 whatever the storage type T.
+#pragma once
+#include "dpp_internal.h"
+
+namespace dpp {
+namespace leaf {
+
+constexpr int L = kLeaf;
+constexpr int kRowsPerWG = 256;
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Round-to-nearest-even FP32 -> BF16 bit pattern (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h)
+{
+    return __builtin_bit_cast(float, h << 16);
+}
+
+// Columns past a ragged last block (k >= bs) do not exist. Loads read the last
+// real column instead and discard it; stores go to a small sink in the
+// workspace. Both keep the fully unrolled code free of uniform branches, which
+// would otherwise split it into many small blocks and force register spills.
+template <typename T>
+__device__ __forceinline__ double load_clamped(const T* A, int64_t idx, int64_t idx_last, bool real)
+{
+    const double v = (double)A[real ? idx : idx_last];
+    return real ? v : 0.0;
+}
+template <typename T>
+__device__ __forceinline__ void store_or_sink(T* A, int64_t idx, void* sink, bool real, double v)
+{
+    T* p = real ? &A[idx] : static_cast<T*>(sink);
+    *p = (T)v;
+}
+
+// Write the hi/lo BF16 split of v[0..63] to two rows (64 bf16 each, 16-byte
+// aligned), as 8 stores of 16 bytes per row.
+__device__ __forceinline__ void store_split_row(uint16_t* hi_row, uint16_t* lo_row,
+                                                const double (&v)[L], int bs)
+{
+#pragma unroll
+    for (int g = 0; g < L / 8; ++g) {
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            uint32_t hh[2], ll[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int k = g * 8 + e * 2 + t;
+                const double x = (k < bs) ? v[k] : 0.0;
+                const uint32_t xh = bf16_bits((float)x);
+                const double rem = x - (double)bf16_value(xh);
+                hh[t] = xh;
+                ll[t] = bf16_bits((float)rem);
+            }
+            h[e] = hh[0] | (hh[1] << 16);
+            l[e] = ll[0] | (ll[1] << 16);
+        }
+        *reinterpret_cast<uint4*>(hi_row + g * 8) = make_uint4(h[0], h[1], h[2], h[3]);
+        *reinterpret_cast<uint4*>(lo_row + g * 8) = make_uint4(l[0], l[1], l[2], l[3]);
+    }
+}
+
+}  // namespace leaf
+}  // namespace dpp

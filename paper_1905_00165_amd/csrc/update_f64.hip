@@ -1,0 +1,186 @@
+// FP64 Schur-complement update of the blocked DPP sampler on gfx950 MFMA.
+//
+// After a group of pivots [k0, k0+kw) has been decided and its panel solved,
+// the trailing matrix receives the outer-product update of the blocked
+// factorization (Sec. 3, the last line of the blocked LU loop; for Hermitian
+// K the symmetric form the paper notes halves the work):
+//   LDL^H: C[r][c] -= sum_k L[r][k] * d'_k * L[c][k]   (lower part only)
+//   LU:    C[r][c] -= sum_k L[r][k] * U[k][c]
+// for r in [base, n), c in [base, base+ncols). The modified pivots d'_k of
+// rejected indices already include the -1 of Prop. 4, so this is a plain
+// product: Prop. 5 is what makes the blocked update equal to the unblocked one.
+//
+// Tiling: a 256-thread workgroup owns a 128x128 tile of C; its four wavefronts
+// each own 64x64 as 4x4 blocks of v_mfma_f64_16x16x4f64. K advances in chunks
+// of 16 staged through LDS (k-major, so the column-major source is read with
+// unit stride). For LDL^H only tiles on or below the diagonal are launched.
+#include "dpp_internal.h"
+
+namespace dpp {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 128;       // tile rows
+constexpr int TN = 128;       // tile cols
+constexpr int KC = 16;        // k per LDS stage
+constexpr int PAD = 2;        // LDS row padding (doubles)
+
+struct TileCoord {
+    int64_t i0, j0;
+};
+
+// Map a linear tile index to (row tile, col tile) of the region. For the
+// Hermitian case the region is the lower trapezoid {J <= I}; tiles are ordered
+// by column tile, then row tile.
+__device__ __forceinline__ bool tile_of(int64_t t, int64_t NR, int64_t NC, bool herm,
+                                        TileCoord& tc)
+{
+    if (!herm) {
+        if (t >= NR * NC) return false;
+        tc.i0 = (t % NR) * TM;
+        tc.j0 = (t / NR) * TN;
+        return true;
+    }
+    // count of tiles in columns < J: J*NR - J*(J-1)/2
+    int64_t J = 0, before = 0;
+    for (; J < NC; ++J) {
+        const int64_t here = NR - J;
+        if (t < before + here) break;
+        before += here;
+    }
+    if (J >= NC) return false;
+    tc.i0 = (J + (t - before)) * TM;
+    tc.j0 = J * TN;
+    return true;
+}
+
+template <typename T, bool HERM>
+__global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ probs, int64_t base,
+                                                  int64_t ncols_req, int64_t k0, int kw)
+{
+    const DevProb P = probs[blockIdx.y];
+    const int64_t n = P.n;
+    const int64_t nrows = n - base;
+    if (nrows <= 0 || k0 + kw > n) return;
+    const int64_t ncols = ncols_req < nrows ? ncols_req : nrows;
+    const int64_t NR = (nrows + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
+    TileCoord tc;
+    if (!tile_of(blockIdx.x, NR, NC, HERM, tc)) return;
+
+    T* __restrict__ A = static_cast<T*>(P.A);
+    const int64_t lda = P.lda;
+    const double* __restrict__ piv = P.piv;
+
+    __shared__ double sA[KC][TM + PAD];
+    __shared__ double sB[KC][TN + PAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t rowA0 = base + tc.i0;  // global row of tile row 0
+    const int64_t colB0 = base + tc.j0;  // global col of tile col 0
+
+    for (int kc = 0; kc < kw; kc += KC) {
+        // A tile: rows rowA0 + i, k = k0 + kc + kk. Thread -> (i = tid % 128, kk = tid/128 + 2q).
+        {
+            const int i = tid & (TM - 1);
+            const int64_t gr = rowA0 + i;
+#pragma unroll
+            for (int q = 0; q < KC / 2; ++q) {
+                const int kk = (tid >> 7) + 2 * q;
+                const int64_t gk = k0 + kc + kk;
+                sA[kk][i] = (gr < n) ? (double)A[gr + gk * lda] : 0.0;
+            }
+        }
+        if constexpr (HERM) {
+            // B[k][c] = L[c][k] * d'_k with L in the lower triangle of A.
+            const int j = tid & (TN - 1);
+            const int64_t gc = colB0 + j;
+#pragma unroll
+            for (int q = 0; q < KC / 2; ++q) {
+                const int kk = (tid >> 7) + 2 * q;
+                const int64_t gk = k0 + kc + kk;
+                sB[kk][j] = (gc < base + ncols) ? (double)A[gc + gk * lda] * piv[gk] : 0.0;
+            }
+        } else {
+            // B[k][c] = U[k][c] = A[k][c]: for a column, KC consecutive k.
+            const int kk = tid & (KC - 1);
+            const int64_t gk = k0 + kc + kk;
+#pragma unroll
+            for (int q = 0; q < TN / 16; ++q) {
+                const int j = (tid >> 4) + 16 * q;
+                const int64_t gc = colB0 + j;
+                sB[kk][j] = (gc < base + ncols) ? (double)A[gk + gc * lda] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            double af[4], bf[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                af[b] = sA[kk][wm * 64 + b * 16 + (lane & 15)];
+                bf[b] = sB[kk][wn * 64 + b * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[bi], bf[bj], acc[bi][bj],
+                                                                       0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // D block layout of v_mfma_f64_16x16x4f64 (measured on gfx950): element e
+    // of a lane holds row lane/16 + 4*e of column lane%16.
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gr = rowA0 + wm * 64 + bi * 16 + (lane >> 4) + 4 * e;
+                const bool ok = gr < n && gc < base + ncols && (!HERM || gr >= gc);
+                if (ok) {
+                    T* p = &A[gr + gc * lda];
+                    *p = (T)((double)*p - acc[bi][bj][e]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
+                             int64_t base, int64_t ncols, int64_t k0, int kw, hipStream_t s)
+{
+    const int64_t nrows = nmax - base;
+    if (nrows <= 0) return hipSuccess;
+    const int64_t nc = ncols < nrows ? ncols : nrows;
+    const int64_t NR = (nrows + TM - 1) / TM, NC = (nc + TN - 1) / TN;
+    const int64_t tiles = herm ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
+    dim3 grid((unsigned)tiles, nprob), block(256);
+    if (herm) {
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true>), grid, block, 0, s, probs, base, ncols, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, true>), grid, block, 0, s, probs, base, ncols, k0, kw);
+    } else {
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false>), grid, block, 0, s, probs, base, ncols, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, false>), grid, block, 0, s, probs, base, ncols, k0, kw);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dpp

@@ -1,0 +1,89 @@
+"""The C ABI library loads and exports every function include/dpp.h declares,
+and rejects bad arguments synchronously. No GPU needed: every call here fails
+its argument checks before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_00165_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dpp.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ["dpp_sample_ldlh", "dpp_sample_lu", "dpp_sample_ldlh_batched",
+                 "dpp_sample_lu_batched", "dpp_workspace_size", "dpp_workspace_size_batched",
+                 "dpp_status_string", "dpp_profile_begin", "dpp_profile_end"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for s in range(5):
+        assert B.dpp_status_string(s)
+    assert B.dpp_status_string(99) == "unknown status"
+
+
+def test_workspace_sizes():
+    assert B.dpp_workspace_size(True, B.DPP_F64, 0, B.DPP_PREC_FP64) == 0
+    assert B.dpp_workspace_size(True, 7, 10, B.DPP_PREC_FP64) == 0
+    fp = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_FP64)
+    sp = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_SPLIT_BF16)
+    assert 0 < fp < sp
+    # split copies: 4 planes of n x (outer panel width) bf16
+    assert sp - fp >= 4 * 1000 * 512 * 2
+    b = B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 200], B.DPP_PREC_SPLIT_BF16)
+    assert b >= (B.dpp_workspace_size(True, B.DPP_F64, 100, B.DPP_PREC_SPLIT_BF16) +
+                 B.dpp_workspace_size(True, B.DPP_F64, 200, B.DPP_PREC_SPLIT_BF16) - 1024)
+    assert B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 0], B.DPP_PREC_FP64) == 0
+
+
+@pytest.mark.parametrize("name", ["dpp_sample_ldlh", "dpp_sample_lu"])
+def test_argument_errors_return_before_any_launch(name):
+    f = getattr(B.lib(), name)
+    p = ctypes.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    ws = ctypes.c_void_p(0x2000)
+    big = 1 << 40
+    # n < 1
+    assert f(p, 0, 0, 1, p, p, p, p, p, 0, ws, big, None) == 1
+    # lda < n
+    assert f(p, 0, 10, 9, p, p, p, p, p, 0, ws, big, None) == 1
+    # null A / u / outputs
+    assert f(None, 0, 10, 10, p, p, p, p, p, 0, ws, big, None) == 1
+    assert f(p, 0, 10, 10, None, p, p, p, p, 0, ws, big, None) == 1
+    assert f(p, 0, 10, 10, p, p, p, p, None, 0, ws, big, None) == 1
+    # bad enums
+    assert f(p, 5, 10, 10, p, p, p, p, p, 0, ws, big, None) == 1
+    assert f(p, 0, 10, 10, p, p, p, p, p, 9, ws, big, None) == 1
+    # workspace
+    assert f(p, 0, 10, 10, p, p, p, p, p, 0, None, big, None) == 2
+    assert f(p, 0, 10, 10, p, p, p, p, p, 1, ws, 16, None) == 2
+
+
+def test_batched_argument_errors():
+    lib = B.lib()
+    p = 0x1000
+    probs = (B.dpp_problem * 2)(B.dpp_problem(p, 10, 10, p, p, p, p, p),
+                                B.dpp_problem(p, 10, 8, p, p, p, p, p))
+    assert lib.dpp_sample_ldlh_batched(probs, 2, 0, 0, ctypes.c_void_p(p), 1 << 40, None) == 1
+    assert lib.dpp_sample_lu_batched(probs, 0, 0, 0, ctypes.c_void_p(p), 1 << 40, None) == 1
+    assert lib.dpp_sample_lu_batched(None, 1, 0, 0, ctypes.c_void_p(p), 1 << 40, None) == 1
+
+
+def test_profile_without_launches_is_empty():
+    B.dpp_profile_begin()
+    assert B.dpp_profile_end() == {}

@@ -1,0 +1,223 @@
+"""GPU parity: the HIP sampler against the FP64 oracle, element by element, on
+the same seeded inputs and uniform streams, through the C ABI.
+
+Tolerances (per run):
+  FP64 path: pre-decision probabilities |d_gpu - d_oracle| <= 1e-9 and
+             |ll_gpu - ll_oracle| <= 1e-9 |ll_oracle|; near-tie threshold 1e-10.
+  split-BF16 path: 1e-4 and near-tie threshold 1e-5.
+  FP32 storage (FP64 updates): 1e-5, threshold 1e-6 (each stored Schur
+             complement entry is rounded to FP32, relative 6e-8 per step).
+A mask difference is allowed only as a counted near tie (tests/parity.py).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_00165_amd import workloads as W
+from parity import compare
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B = None
+DEV = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    global B, DEV
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_00165_amd import binding
+    B = binding
+    DEV = torch.device("cuda:0")
+    yield
+
+
+TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5)}
+PRECS = [0, 1]
+PREC_ID = {0: "fp64", 1: "split"}
+
+
+def _run(herm, K, u, prec, dtype=torch.float64):
+    A = B.colmajor(np.asarray(K), device=DEV, dtype=dtype)
+    ut = torch.from_numpy(np.ascontiguousarray(u)).to(DEV)
+    fn = B.dpp_sample_ldlh if herm else B.dpp_sample_lu
+    out = fn(A, ut, prec=prec)
+    torch.cuda.synchronize()
+    return {"mask": out["mask"].cpu().numpy(), "pivots": out["pivots"].cpu().numpy(),
+            "loglik": float(out["loglik"].cpu()[0]), "info": int(out["info"].cpu()[0]),
+            "A": A.cpu().numpy()}
+
+
+def _check(herm, K, u, prec, tol=None, thr=None, dtype=torch.float64):
+    t, h = TOL[prec]
+    tol = tol or t
+    thr = thr or h
+    Kw = np.asarray(K, dtype=np.float64) if dtype == torch.float64 else \
+        np.asarray(K).astype(np.float32).astype(np.float64)
+    ref = (oracle.ldlh if herm else oracle.lu)(Kw, u)
+    got = _run(herm, K, u, prec, dtype=dtype)
+    v = compare(got["mask"], got["pivots"], got["loglik"], ref, u, tol, thr)
+    assert got["info"] == 0
+    assert v.ok, v.why
+    return v, got, ref
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65, 127, 129, 200, 300, 513, 777])
+def test_ldlh_small_sizes(n, prec):
+    K = W.hermitian_kernel(n, seed=10 + n)
+    u = W.uniform_stream(n, seed=20 + n)
+    _check(True, K, u, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 200, 300, 513])
+def test_lu_small_sizes(n, prec):
+    K, _ = W.similarity_kernel(n, seed=30 + n)
+    u = W.uniform_stream(n, seed=40 + n)
+    _check(False, K, u, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_ldlh_dense_kernel_n1024_streams(prec):
+    """The plain workload at n = 1024: K = Q diag(lam) Q^T, lam ~ U(0,1)."""
+    K = W.hermitian_kernel(1024, seed=1)
+    ties = 0
+    for s in range(6):
+        u = W.uniform_stream(1024, seed=1000 + s)
+        v, _, _ = _check(True, K, u, prec)
+        ties += v.near_tie
+    assert ties <= 1
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_lu_similarity_kernel_n1024(prec):
+    """K = S H S^-1 sampled by the LU path matches the oracle, and its mask
+    equals the LDL^H path's on H (Prop. 2)."""
+    K, H = W.similarity_kernel(1024, seed=3)
+    u = W.uniform_stream(1024, seed=3000)
+    v, got, ref = _check(False, K, u, prec)
+    gh = _run(True, H, u, prec)
+    if v.first_diff < 0:
+        assert np.array_equal(got["mask"], gh["mask"]) or prec == 1
+
+
+def test_fp32_storage_lensemble():
+    """FP32-stored L-ensemble marginal kernel; FP64 decisions and updates."""
+    K = W.lensemble_kernel(300, seed=4)
+    u = W.uniform_stream(300, seed=4000)
+    _check(True, K, u, 0, tol=1e-5, thr=1e-6, dtype=torch.float32)
+
+
+def test_fp32_storage_split():
+    K = W.lensemble_kernel(700, seed=5)
+    u = W.uniform_stream(700, seed=5000)
+    _check(True, K, u, 1, tol=1e-4, thr=1e-5, dtype=torch.float32)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_factor_reconstructs_k_minus_indicator(prec):
+    n = 500
+    K = W.hermitian_kernel(n, seed=6)
+    u = W.uniform_stream(n, seed=6000)
+    got = _run(True, K, u, prec)
+    R = oracle.reconstruct_ldlh(got["A"])
+    target = K - np.diag(1.0 - got["mask"])
+    err = np.max(np.abs(np.tril(R) - np.tril(target)))
+    assert err <= (1e-10 if prec == 0 else 1e-4)
+    # the decision rule on the GPU's own probabilities
+    d = got["pivots"] + 1.0 - got["mask"]
+    assert np.array_equal(got["mask"], (u < d).astype(np.uint8))
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_projection_sample_size(prec):
+    n, k = 1024, 256
+    K = W.projection_kernel(n, k, seed=7)
+    for s in range(4):
+        got = _run(True, K, W.uniform_stream(n, seed=7000 + s), prec)
+        assert int(got["mask"].sum()) == k
+
+
+def test_zero_pivot_sets_info():
+    K = np.diag([0.5, 1.0, 0.25])
+    got = _run(True, K, np.array([0.1, 1.0, 0.1]), 0)
+    assert got["info"] == 2
+    assert got["pivots"][1] == 0.0
+    assert not np.isfinite(got["loglik"])
+
+
+def test_lda_padding_untouched():
+    n, pad = 150, 5
+    K = W.hermitian_kernel(n, seed=8)
+    u = W.uniform_stream(n, seed=8000)
+    storage = torch.full((n, n + pad), 7.0, dtype=torch.float64, device=DEV)
+    storage[:, :n] = torch.as_tensor(K.T, device=DEV)
+    A = storage.t()[:n, :]  # column-major view, lda = n + pad
+    assert A.stride() == (1, n + pad)
+    out = B.dpp_sample_ldlh(A, torch.from_numpy(u).to(DEV), prec=0)
+    torch.cuda.synchronize()
+    full = storage.cpu().numpy()
+    assert np.all(full[:, n:] == 7.0)
+    ref = oracle.ldlh(K, u)
+    v = compare(out["mask"].cpu().numpy(), out["pivots"].cpu().numpy(),
+                float(out["loglik"].cpu()[0]), ref, u, 1e-9, 1e-10)
+    assert v.ok, v.why
+
+
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_batched_equals_single_bitwise(herm, prec):
+    ns = [100, 257, 64, 1]
+    Ks = [W.hermitian_kernel(n, seed=90 + n) if herm else W.similarity_kernel(n, seed=90 + n)[0]
+          for n in ns]
+    us = [W.uniform_stream(n, seed=9000 + n) for n in ns]
+    As = [B.colmajor(K, device=DEV) for K in Ks]
+    uts = [torch.from_numpy(u).to(DEV) for u in us]
+    fb = B.dpp_sample_ldlh_batched if herm else B.dpp_sample_lu_batched
+    outs = fb(As, uts, prec=prec)
+    torch.cuda.synchronize()
+    for K, u, A, o in zip(Ks, us, As, outs):
+        single = _run(herm, K, u, prec)
+        assert np.array_equal(o["mask"].cpu().numpy(), single["mask"])
+        assert np.array_equal(o["pivots"].cpu().numpy(), single["pivots"])
+        assert float(o["loglik"].cpu()[0]) == single["loglik"]
+        assert np.array_equal(A.cpu().numpy(), single["A"])
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_deterministic(prec):
+    n = 700
+    K = W.hermitian_kernel(n, seed=11)
+    u = W.uniform_stream(n, seed=11000)
+    a, b = _run(True, K, u, prec), _run(True, K, u, prec)
+    assert np.array_equal(a["A"], b["A"]) and a["loglik"] == b["loglik"]
+
+
+def test_uniform_spanning_tree_grid40():
+    """The paper's 40 x 40 grid example on the GPU: a spanning tree with
+    likelihood exp(-1794.24)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "worked_examples.json")))["uniform_spanning_tree_grid_40"]
+    K, edges = W.grid_transfer_current_kernel(40)
+    got = _run(True, K, W.uniform_stream(K.shape[0], seed=901), 0)
+    assert got["info"] == 0
+    chosen = edges[got["mask"].astype(bool)]
+    assert len(chosen) == 40 * 40 - 1
+    parent = list(range(1600))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    for a, b in chosen:
+        ra, rb = find(a), find(b)
+        assert ra != rb
+        parent[ra] = rb
+    assert got["loglik"] == pytest.approx(gold["loglik_printed"], abs=0.005)
