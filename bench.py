@@ -44,6 +44,11 @@ def parse():
     p.add_argument("--prec", choices=["both", "split", "fp64"], default="both")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target length of the CPU oracle baseline sample (0: skip)")
+    p.add_argument("--k-cache", default=None,
+                   help="npy file holding K: loaded if present, else written after generation "
+                        "(lets profiled runs skip the QR of the generator)")
+    p.add_argument("--prepare-only", action="store_true",
+                   help="generate (and cache) K, then exit")
     return p.parse_args()
 
 
@@ -137,8 +142,17 @@ def main():
 
     dev = torch.device("cuda:0")
     n, r, bsz = args.n, args.rank, args.batch
-    log(f"[bench] generating K: n={n} rank={r}")
-    K = W.projection_kernel(n, r, seed=2, device=dev)          # (n, n) row-major == K^T == K
+    if args.k_cache and os.path.exists(args.k_cache):
+        log(f"[bench] loading K from {args.k_cache}")
+        K = torch.from_numpy(np.load(args.k_cache, mmap_mode="r")[:]).to(dev)
+        assert K.shape == (n, n)
+    else:
+        log(f"[bench] generating K: n={n} rank={r}")
+        K = W.projection_kernel(n, r, seed=2, device=dev)      # (n, n) row-major == K^T == K
+        if args.k_cache:
+            np.save(args.k_cache, K.cpu().numpy())
+    if args.prepare_only:
+        return
     us = [torch.from_numpy(W.uniform_stream(n, seed=2000 + i)).to(dev) for i in range(bsz)]
     As = [torch.empty_like(K) for _ in range(bsz)]
     torch.cuda.synchronize()

@@ -4,7 +4,7 @@
 // Launch sequence (blocked right-looking sampler, Sec. 3; the unblocked
 // sampler of Sec. 2 on each 64-wide diagonal block):
 //
-//   LDL^H, outer block width B0 (FP64: 256, split-BF16: 512):
+//   LDL^H, outer block width B0 (FP64: 256, split-BF16: 1024):
 //     for each outer panel [j0, j1):
 //       factor_panel(j0, j1)                       -- recursive, below
 //       update rows/cols [j1, n) by columns [j0, j1) -- the trailing update
@@ -47,7 +47,10 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec)
     p.herm = herm;
     p.dtype = (dt == DPP_F32) ? 1 : 0;
     p.split = (prec == DPP_PREC_SPLIT_BF16);
-    if (herm) p.B0 = p.split ? 512 : 256;
+    // Outer panel width: each trailing update reads and writes the trailing
+    // matrix once, so its HBM traffic per sample is ~ 8 n^3 / (3 B0) bytes for
+    // FP64 storage; the split path needs the wider panel to stay MFMA-bound.
+    if (herm) p.B0 = p.split ? 1024 : 256;
     else p.B0 = kLeaf;
     p.ss = p.B0;
     return p;
@@ -60,8 +63,14 @@ size_t split_bytes(const Plan& p, int64_t n)
 {
     return p.split ? align_up((size_t)4 * (size_t)n * (size_t)p.ss * sizeof(uint16_t)) : 0;
 }
-// Workspace layout: [descriptors][sink, kAlign bytes][split copies per problem].
-size_t desc_bytes(int64_t count) { return align_up((size_t)count * sizeof(DevProb)) + kAlign; }
+size_t diag_bytes(int64_t n)
+{
+    return align_up((size_t)((n + kLeaf - 1) / kLeaf) * kLeaf * kLeaf * sizeof(double));
+}
+// Per-problem workspace: [diagonal-block strip][split copies].
+size_t problem_bytes(const Plan& p, int64_t n) { return diag_bytes(n) + split_bytes(p, n); }
+// Workspace layout: [descriptors][per problem: diagonal strip, split copies].
+size_t desc_bytes(int64_t count) { return align_up((size_t)count * sizeof(DevProb)); }
 
 bool valid_enums(dpp_dtype dt, dpp_precision prec)
 {
@@ -88,9 +97,12 @@ dpp_status device_ok()
 
 // ------------------------------------------------------------------ profiling
 // Kernel families whose launches the profiler tells apart.
-enum KernelId { K_LEAF_LDLH, K_LEAF_LU, K_UPDATE_F64, K_UPDATE_BF16X3, K_FINALIZE, K_DESCS, K_COUNT };
-const char* const kKernelNames[K_COUNT] = {"leaf_ldlh", "leaf_lu", "update_f64", "update_bf16x3",
-                                           "finalize", "store_descs"};
+enum KernelId {
+    K_LEAF_LDLH, K_LEAF_LU, K_UPDATE_F64, K_UPDATE_BF16X3, K_STORE_DIAG, K_FINALIZE, K_DESCS,
+    K_COUNT
+};
+const char* const kKernelNames[K_COUNT] = {"leaf_ldlh", "leaf_lu",    "update_f64", "update_bf16x3",
+                                           "store_diag", "finalize", "store_descs"};
 
 struct ProfRecord {
     int id;
@@ -246,7 +258,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
             return DPP_ERR_INVALID_ARG;
         if (q.n > (int64_t)1 << 31) return DPP_ERR_INVALID_ARG;
         nmax = q.n > nmax ? q.n : nmax;
-        need += split_bytes(plan, q.n);
+        need += problem_bytes(plan, q.n);
     }
     if (!ws || ws_bytes < need) return DPP_ERR_WORKSPACE;
     const dpp_status dev = device_ok();
@@ -254,7 +266,6 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
 
     std::vector<DevProb> host((size_t)count);
     char* cursor = static_cast<char*>(ws) + desc_bytes(count);
-    void* sink = cursor - kAlign;
     for (int64_t i = 0; i < count; ++i) {
         const dpp_problem& q = probs[i];
         DevProb& d = host[(size_t)i];
@@ -266,9 +277,9 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.piv = q.pivots;
         d.loglik = q.loglik;
         d.info = q.info;
-        d.split = plan.split ? reinterpret_cast<uint16_t*>(cursor) : nullptr;
-        d.sink = sink;
-        cursor += split_bytes(plan, q.n);
+        d.diag = reinterpret_cast<double*>(cursor);
+        d.split = plan.split ? reinterpret_cast<uint16_t*>(cursor + diag_bytes(q.n)) : nullptr;
+        cursor += problem_bytes(plan, q.n);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<int64_t> ns((size_t)count);
@@ -299,6 +310,10 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
             if (st != DPP_OK) return st;
         }
     }
+    dpp_status st = timed(c, K_STORE_DIAG, 0.0, 0.0, [&] {
+        return dpp::launch_store_diag(plan.herm, plan.dtype, c.probs, c.count, nmax, s);
+    });
+    if (st != DPP_OK) return st;
     return timed(c, K_FINALIZE, 0.0, 0.0, [&] { return dpp::launch_finalize(c.probs, c.count, s); });
 }
 
@@ -310,7 +325,7 @@ size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t cou
     size_t need = desc_bytes(count);
     for (int64_t i = 0; i < count; ++i) {
         if (ns[i] < 1) return 0;
-        need += split_bytes(plan, ns[i]);
+        need += problem_bytes(plan, ns[i]);
     }
     return need;
 }

@@ -22,8 +22,8 @@ struct DevProb {
     double* loglik;   // 1
     int32_t* info;    // 1
     uint16_t* split;  // split-BF16 panel copies (see below), or nullptr
-    void* sink;       // 16 bytes of workspace that absorb stores to columns past a
-                      // ragged last block (never read)
+    double* diag;     // ceil(n/64) factored 64x64 diagonal blocks, column-major,
+                      // block b at diag[b * 64 * 64]; copied into A at the end
 };
 
 // Split-BF16 panel copies of problem p live at split[q * n * ss + r * ss + kk],
@@ -60,9 +60,14 @@ hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int 
 // loglik (fixed-order sum of ln|piv|) and info, one workgroup per problem.
 hipError_t launch_finalize(const DevProb* probs, int nprob, hipStream_t s);
 
+// Copies the factored diagonal blocks from each problem's strip into A (lower
+// part for LDL^H, whole block for LU).
+hipError_t launch_store_diag(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
+                             hipStream_t s);
+
 // Copy `cnt` (<= kDescPerLaunch) host descriptors to dst through the kernel
 // argument block of a one-workgroup launch.
-constexpr int kDescPerLaunch = 48;
+constexpr int kDescPerLaunch = 44;
 hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStream_t s);
 
 }  // namespace dpp

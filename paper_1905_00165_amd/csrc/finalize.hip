@@ -45,6 +45,22 @@ __global__ __launch_bounds__(kThreads) void finalize(const DevProb* __restrict__
     }
 }
 
+template <typename T, bool HERM>
+__global__ __launch_bounds__(256) void store_diag(const DevProb* __restrict__ probs)
+{
+    const DevProb P = probs[blockIdx.y];
+    const int64_t c0 = (int64_t)blockIdx.x * kLeaf;
+    if (c0 >= P.n) return;
+    const int bs = (int)((P.n - c0) < kLeaf ? (P.n - c0) : kLeaf);
+    const double* blk = P.diag + (int64_t)blockIdx.x * kLeaf * kLeaf;
+    T* A = static_cast<T*>(P.A);
+    for (int e = threadIdx.x; e < kLeaf * kLeaf; e += 256) {
+        const int i = e % kLeaf, k = e / kLeaf;
+        if (i < bs && k < bs && (!HERM || k <= i))
+            A[(c0 + i) + (c0 + k) * P.lda] = (T)blk[e];
+    }
+}
+
 struct DescChunk {
     DevProb d[kDescPerLaunch];
     int cnt;
@@ -64,6 +80,20 @@ hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStr
     for (int i = 0; i < cnt; ++i) chunk.d[i] = host[i];
     chunk.cnt = cnt;
     hipLaunchKernelGGL(store_descs, dim3(1), dim3(64), 0, s, chunk, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_diag(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
+                             hipStream_t s)
+{
+    dim3 grid((unsigned)((nmax + kLeaf - 1) / kLeaf), nprob);
+    if (herm) {
+        if (dtype == 0) hipLaunchKernelGGL((store_diag<double, true>), grid, dim3(256), 0, s, probs);
+        else hipLaunchKernelGGL((store_diag<float, true>), grid, dim3(256), 0, s, probs);
+    } else {
+        if (dtype == 0) hipLaunchKernelGGL((store_diag<double, false>), grid, dim3(256), 0, s, probs);
+        else hipLaunchKernelGGL((store_diag<float, false>), grid, dim3(256), 0, s, probs);
+    }
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ namespace dpp {
 namespace leaf {
 
 constexpr int L = kLeaf;
-constexpr int kRowsPerWG = 256;
+constexpr int kRowsPerWG = 512;  // one panel row per thread; 8 wavefronts
 
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
@@ -46,21 +46,43 @@ __device__ __forceinline__ float bf16_value(uint32_t h)
     return __builtin_bit_cast(float, h << 16);
 }
 
-// Columns past a ragged last block (k >= bs) do not exist. Loads read the last
-// real column instead and discard it; stores go to a small sink in the
-// workspace. Both keep the fully unrolled code free of uniform branches, which
-// would otherwise split it into many small blocks and force register spills.
-template <typename T>
-__device__ __forceinline__ double load_clamped(const T* A, int64_t idx, int64_t idx_last, bool real)
+// Raw buffer access to a column strip of A: base points at the strip's first
+// element, `voff` is a per-lane byte offset and `soff` a per-column byte
+// offset held in a scalar register, so a lane's 64 column loads share one
+// address register and issue back to back.
+constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format, gfx9 resource word 3
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t strip_rsrc(const void* base, int64_t bytes)
 {
-    const double v = (double)A[real ? idx : idx_last];
-    return real ? v : 0.0;
+    const int nrec = bytes > 0x7fffffff ? 0x7fffffff : (int)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, nrec, kBufFlags);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 template <typename T>
-__device__ __forceinline__ void store_or_sink(T* A, int64_t idx, void* sink, bool real, double v)
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
 {
-    T* p = real ? &A[idx] : static_cast<T*>(sink);
-    *p = (T)v;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store<float>(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, voff, soff, 0);
 }
 
 // Write the hi/lo BF16 split of v[0..63] to two rows (64 bf16 each, 16-byte

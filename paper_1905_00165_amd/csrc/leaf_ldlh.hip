@@ -8,7 +8,7 @@ using namespace leaf;
 
 // ------------------------------------------------------------------- LDL^H
 template <typename T, bool SPLIT>
-__global__ __launch_bounds__(256) void leaf_ldlh(const DevProb* __restrict__ probs, int64_t c0,
+__global__ __launch_bounds__(kRowsPerWG) void leaf_ldlh(const DevProb* __restrict__ probs, int64_t c0,
                                                  int64_t j0, int ss)
 {
     const DevProb P = probs[blockIdx.y];
@@ -67,10 +67,14 @@ __global__ __launch_bounds__(256) void leaf_ldlh(const DevProb* __restrict__ pro
         for (int k = 0; k < L; ++k) sL[k * L + lane] = (k < lane && lane < bs) ? a[k] : 0.0;
         sD[lane] = (lane < bs) ? mydp : 1.0;
 
+        // The factored block goes to the workspace strip, not to A: other
+        // workgroups of this launch may still be loading the original block
+        // from A for their own copy of the chain. A later launch copies the
+        // strip into A (no kernel reads the diagonal blocks from A).
         if (blockIdx.x == 0 && lane < bs) {
+            double* blk = P.diag + (c0 / L) * (L * L);
 #pragma unroll
-            for (int k = 0; k < L; ++k)
-                if (k <= lane) A[(c0 + lane) + (c0 + k) * lda] = (T)a[k];
+            for (int k = 0; k < L; ++k) blk[k * L + lane] = a[k];
             P.mask[c0 + lane] = (uint8_t)mykeep;
             P.piv[c0 + lane] = mydp;
         }
@@ -78,12 +82,19 @@ __global__ __launch_bounds__(256) void leaf_ldlh(const DevProb* __restrict__ pro
     __syncthreads();
 
     // Panel solve: row r of A21 becomes W = A21 L11^{-T} (= L21 D1), then
-    // L21 = W D1^{-1}.
+    // L21 = W D1^{-1}. Rows below a block exist only when the block is a full
+    // 64 wide (a ragged block is the last one), so bs == L here.
     const int64_t r = row0 + tid;
     if (r < n) {
+        // Strip = columns [c0, c0+64) from row row0 on; lane offset tid rows,
+        // column k at k * lda elements.
+        const __amdgpu_buffer_rsrc_t rs =
+            strip_rsrc(A + row0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
+        const int voff = tid * (int)sizeof(T);
+        const int cstride = (int)(lda * (int64_t)sizeof(T));
         double x[L];
 #pragma unroll
-        for (int k = 0; k < L; ++k) x[k] = load_clamped(A, r + (c0 + k) * lda, r + (c0 + bs - 1) * lda, k < bs);
+        for (int k = 0; k < L; ++k) x[k] = buf_load<T>(rs, voff, k * cstride);
 #pragma unroll
         for (int t = 0; t < L; ++t) {
             const double wt = x[t];
@@ -95,17 +106,17 @@ __global__ __launch_bounds__(256) void leaf_ldlh(const DevProb* __restrict__ pro
             // W = L21 D1 first, then x becomes L21 in place.
             const int64_t off = r * ss + (int)(c0 - j0);
             store_split_row(split_plane(P.split, n, ss, 2) + off,
-                            split_plane(P.split, n, ss, 3) + off, x, bs);
+                            split_plane(P.split, n, ss, 3) + off, x, L);
         }
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             x[k] = x[k] / sD[k];
-            store_or_sink(A, r + (c0 + k) * lda, P.sink, k < bs, x[k]);
+            buf_store<T>(x[k], rs, voff, k * cstride);
         }
         if constexpr (SPLIT) {
             const int64_t off = r * ss + (int)(c0 - j0);
             store_split_row(split_plane(P.split, n, ss, 0) + off,
-                            split_plane(P.split, n, ss, 1) + off, x, bs);
+                            split_plane(P.split, n, ss, 1) + off, x, L);
         }
     }
 }
@@ -116,7 +127,7 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
 {
     const int64_t below = nmax - c0 - L;
     const int gx = below > 0 ? (int)((below + kRowsPerWG - 1) / kRowsPerWG) : 1;
-    dim3 grid(gx, nprob), block(256);
+    dim3 grid(gx, nprob), block(kRowsPerWG);
     if (split) hipLaunchKernelGGL((leaf_ldlh<T, true>), grid, block, 0, s, probs, c0, j0, ss);
     else hipLaunchKernelGGL((leaf_ldlh<T, false>), grid, block, 0, s, probs, c0, j0, ss);
     return hipGetLastError();

@@ -8,7 +8,7 @@ using namespace leaf;
 
 // ---------------------------------------------------------------------- LU
 template <typename T, bool SPLIT>
-__global__ __launch_bounds__(256) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
+__global__ __launch_bounds__(kRowsPerWG) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
                                                int64_t j0, int ss)
 {
     const DevProb P = probs[blockIdx.y];
@@ -72,55 +72,70 @@ __global__ __launch_bounds__(256) void leaf_lu(const DevProb* __restrict__ probs
             sU[lane * L + k] = (k >= lane && lane < bs) ? a[k] : (k == lane ? 1.0 : 0.0);
         }
 
+        // The factored block goes to the workspace strip, not to A: other
+        // workgroups of this launch may still be loading the original block
+        // from A for their own copy of the chain. A later launch copies the
+        // strip into A (no kernel reads the diagonal blocks from A).
         if (blockIdx.x == 0 && lane < bs) {
+            double* blk = P.diag + (c0 / L) * (L * L);
 #pragma unroll
-            for (int k = 0; k < L; ++k)
-                if (k < bs) A[(c0 + lane) + (c0 + k) * lda] = (T)a[k];
+            for (int k = 0; k < L; ++k) blk[k * L + lane] = a[k];
             P.mask[c0 + lane] = (uint8_t)mykeep;
             P.piv[c0 + lane] = mydp;
         }
     }
     __syncthreads();
 
+    // Rows below and columns right of a block exist only when the block is a
+    // full 64 wide (a ragged block is the last one), so bs == L here.
     const int64_t r = idx0 + tid;
     if (r < n) {
+        const int voff = tid * (int)sizeof(T);
+        const int cstride = (int)(lda * (int64_t)sizeof(T));
         // Column panel: L21 = A21 U11^{-1}, row r: x U11 = a.
-        double x[L];
+        {
+            const __amdgpu_buffer_rsrc_t rs =
+                strip_rsrc(A + idx0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
+            double x[L];
 #pragma unroll
-        for (int k = 0; k < L; ++k) x[k] = load_clamped(A, r + (c0 + k) * lda, r + (c0 + bs - 1) * lda, k < bs);
+            for (int k = 0; k < L; ++k) x[k] = buf_load<T>(rs, voff, k * cstride);
 #pragma unroll
-        for (int t = 0; t < L; ++t) {
-            x[t] = x[t] / sU[t * L + t];
-            const double xt = x[t];
+            for (int t = 0; t < L; ++t) {
+                x[t] = x[t] / sU[t * L + t];
+                const double xt = x[t];
 #pragma unroll
-            for (int k = 0; k < L; ++k)
-                if (k > t) x[k] -= xt * sU[t * L + k];
+                for (int k = 0; k < L; ++k)
+                    if (k > t) x[k] -= xt * sU[t * L + k];
+            }
+#pragma unroll
+            for (int k = 0; k < L; ++k) buf_store<T>(x[k], rs, voff, k * cstride);
+            if constexpr (SPLIT) {
+                const int64_t off = r * ss + (int)(c0 - j0);
+                store_split_row(split_plane(P.split, n, ss, 0) + off,
+                                split_plane(P.split, n, ss, 1) + off, x, L);
+            }
         }
+        // Row panel: U12 = L11^{-1} A12, column r: L11 y = a (64 contiguous
+        // entries of column r).
+        {
+            T* col = A + c0 + r * lda;
+            double y[L];
 #pragma unroll
-        for (int k = 0; k < L; ++k) store_or_sink(A, r + (c0 + k) * lda, P.sink, k < bs, x[k]);
-        if constexpr (SPLIT) {
-            const int64_t off = r * ss + (int)(c0 - j0);
-            store_split_row(split_plane(P.split, n, ss, 0) + off,
-                            split_plane(P.split, n, ss, 1) + off, x, bs);
-        }
-
-        // Row panel: U12 = L11^{-1} A12, column r: L11 y = a.
-        double y[L];
+            for (int k = 0; k < L; ++k) y[k] = (double)col[k];
 #pragma unroll
-        for (int k = 0; k < L; ++k) y[k] = load_clamped(A, (c0 + k) + r * lda, (c0 + bs - 1) + r * lda, k < bs);
+            for (int t = 0; t < L; ++t) {
+                const double yt = y[t];
 #pragma unroll
-        for (int t = 0; t < L; ++t) {
-            const double yt = y[t];
+                for (int k = 0; k < L; ++k)
+                    if (k > t) y[k] -= yt * sL[t * L + k];
+            }
 #pragma unroll
-            for (int k = 0; k < L; ++k)
-                if (k > t) y[k] -= yt * sL[t * L + k];
-        }
-#pragma unroll
-        for (int k = 0; k < L; ++k) store_or_sink(A, (c0 + k) + r * lda, P.sink, k < bs, y[k]);
-        if constexpr (SPLIT) {
-            const int64_t off = r * ss + (int)(c0 - j0);
-            store_split_row(split_plane(P.split, n, ss, 2) + off,
-                            split_plane(P.split, n, ss, 3) + off, y, bs);
+            for (int k = 0; k < L; ++k) col[k] = (T)y[k];
+            if constexpr (SPLIT) {
+                const int64_t off = r * ss + (int)(c0 - j0);
+                store_split_row(split_plane(P.split, n, ss, 2) + off,
+                                split_plane(P.split, n, ss, 3) + off, y, L);
+            }
         }
     }
 }
@@ -131,7 +146,7 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
 {
     const int64_t below = nmax - c0 - L;
     const int gx = below > 0 ? (int)((below + kRowsPerWG - 1) / kRowsPerWG) : 1;
-    dim3 grid(gx, nprob), block(256);
+    dim3 grid(gx, nprob), block(kRowsPerWG);
     if (split) hipLaunchKernelGGL((leaf_lu<T, true>), grid, block, 0, s, probs, c0, j0, ss);
     else hipLaunchKernelGGL((leaf_lu<T, false>), grid, block, 0, s, probs, c0, j0, ss);
     return hipGetLastError();

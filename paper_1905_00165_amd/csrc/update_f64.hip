@@ -14,6 +14,8 @@
 // each own 64x64 as 4x4 blocks of v_mfma_f64_16x16x4f64. K advances in chunks
 // of 16 staged through LDS (k-major, so the column-major source is read with
 // unit stride). For LDL^H only tiles on or below the diagonal are launched.
+// Workgroup b runs tile (b % 8) * (G / 8) + b / 8 (G, the grid size, is a
+// multiple of 8), so each XCD takes a contiguous range of tiles.
 #include "dpp_internal.h"
 
 namespace dpp {
@@ -65,8 +67,11 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
     if (nrows <= 0 || k0 + kw > n) return;
     const int64_t ncols = ncols_req < nrows ? ncols_req : nrows;
     const int64_t NR = (nrows + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
+    // XCD-contiguous tile order (grid size is a multiple of 8).
+    const int64_t per_xcd = gridDim.x / 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     TileCoord tc;
-    if (!tile_of(blockIdx.x, NR, NC, HERM, tc)) return;
+    if (!tile_of(t, NR, NC, HERM, tc)) return;
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
@@ -136,29 +141,38 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[bi], bf[bj], acc[bi][bj],
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], acc[bi][bj],
                                                                        0, 0, 0);
         }
         __syncthreads();
     }
 
     // D block layout of v_mfma_f64_16x16x4f64 (measured on gfx950): element e
-    // of a lane holds row lane/16 + 4*e of column lane%16.
+    // of lane l is row l/16 + 4e, column l%16 of the product. The column
+    // operand goes first, so lane l holds C row l%16 and C columns l/16 + 4e:
+    // 16 lanes cover 16 consecutive rows of one column of column-major C.
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
+        const int64_t gr = rowA0 + wm * 64 + bi * 16 + (lane & 15);
+        T* const rowp = A + gr;
+        // All loads of this 16-row block before any store (see update_bf16x3.hip).
+        double cv[4][4];
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-            const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane & 15);
+        for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t gr = rowA0 + wm * 64 + bi * 16 + (lane >> 4) + 4 * e;
+                const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
                 const bool ok = gr < n && gc < base + ncols && (!HERM || gr >= gc);
-                if (ok) {
-                    T* p = &A[gr + gc * lda];
-                    *p = (T)((double)*p - acc[bi][bj][e]);
-                }
+                cv[bj][e] = ok ? (double)rowp[gc * lda] : 0.0;
             }
-        }
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
+                const bool ok = gr < n && gc < base + ncols && (!HERM || gr >= gc);
+                if (ok) rowp[gc * lda] = (T)(cv[bj][e] - acc[bi][bj][e]);
+            }
     }
 }
 
@@ -172,7 +186,7 @@ hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int npr
     const int64_t nc = ncols < nrows ? ncols : nrows;
     const int64_t NR = (nrows + TM - 1) / TM, NC = (nc + TN - 1) / TN;
     const int64_t tiles = herm ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
-    dim3 grid((unsigned)tiles, nprob), block(256);
+    dim3 grid((unsigned)((tiles + 7) / 8 * 8), nprob), block(256);
     if (herm) {
         if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true>), grid, block, 0, s, probs, base, ncols, k0, kw);
         else hipLaunchKernelGGL((update_f64<float, true>), grid, block, 0, s, probs, base, ncols, k0, kw);

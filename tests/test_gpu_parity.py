@@ -221,3 +221,26 @@ def test_uniform_spanning_tree_grid40():
         assert ra != rb
         parent[ra] = rb
     assert got["loglik"] == pytest.approx(gold["loglik_printed"], abs=0.005)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_batched_more_workgroups_than_fit_at_once(prec):
+    """12 projection kernels of n = 6144 in one batched call: each diagonal-block
+    launch has more workgroups (23 per problem) than the GPU runs at once, so
+    late workgroups start after workgroup 0 has finished its block. Every sample
+    must still have |Y| = rank and equal the single-problem result."""
+    n, k, count = 6144, 1536, 12
+    K = W.projection_kernel(n, k, seed=12, device=DEV).to(torch.float64)
+    us = [torch.from_numpy(W.uniform_stream(n, seed=12000 + i)).to(DEV) for i in range(count)]
+    As = [K.clone() for _ in range(count)]
+    outs = B.dpp_sample_ldlh_batched([A.t() for A in As], us, prec=prec)
+    torch.cuda.synchronize()
+    sizes = [int(o["mask"].sum().item()) for o in outs]
+    assert sizes == [k] * count
+    for i in (0, count - 1):
+        A1 = K.clone()
+        single = B.dpp_sample_ldlh(A1.t(), us[i], prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(single["mask"], outs[i]["mask"])
+        assert torch.equal(single["pivots"], outs[i]["pivots"])
+        assert torch.equal(A1, As[i])
