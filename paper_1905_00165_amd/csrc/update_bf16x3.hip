@@ -12,23 +12,26 @@
 // consecutive k one MFMA lane holds:
 //   rows of C: hi/lo of L;  cols of C: hi/lo of W = L D (LDL^H) or of U^T (LU).
 //
-// Tiling: 256 threads (4 wavefronts) own a 256x256 tile of C; wavefront
-// (wr, wc) owns 128x128 as 4x4 blocks of 32x32, so each 16-k step reads 16
-// fragments from LDS and issues 48 MFMAs. K advances 32 at a time through two
-// LDS buffers of 64 KiB (one 16 KiB plane per operand). Global -> LDS copies
-// use the gfx950 direct-to-LDS loads (global_load_lds_dwordx4): wavefront w
-// fills plane w, each instruction writing 1 KiB (16 rows x 64 bytes); stage
-// s+1 is in flight while stage s is multiplied, one barrier per stage. LDS rows
-// are 64 bytes with their four 16-byte segments XOR-swizzled by row, so the
-// fragment reads of consecutive rows spread over the banks.
+// Tiling (template Shape): a workgroup owns a TM x TN tile of C split over
+// WR x WC wavefronts, each owning RB x CB blocks of 32x32 (wide shape:
+// 256x256 on 4 wavefronts of 128x128, so each 16-k step reads 16 fragments
+// from LDS and issues 48 MFMAs; narrower shapes serve the narrow updates inside
+// a panel). K advances 32 at a time through two LDS buffers holding the four
+// operand planes. Global -> LDS copies use the gfx950 direct-to-LDS loads
+// (global_load_lds_dwordx4), each instruction writing 1 KiB (16 rows x 64
+// bytes); stage s+1 is in flight while stage s is multiplied, one barrier per
+// stage. LDS rows are 64 bytes with their four 16-byte segments XOR-swizzled by
+// row, so the fragment reads of consecutive rows spread over the banks.
 // The MFMA takes the column operand first, so each lane's accumulators map to
 // one row of C and lanes 0-31 cover 32 consecutive rows of a column: the
 // read-modify-write of column-major C is coalesced. Operand rows past the end
 // of the region are read from the last valid row instead: they only feed
 // accumulators that are never stored.
 // Workgroup b runs tile (b % 8) * (G / 8) + b / 8 (G the grid size, a multiple
-// of 8): the 8 XCDs each take a contiguous range of tiles, which share operand
-// panels in that XCD's L2.
+// of 8): the 8 XCDs each take a contiguous range of tiles. In the wide shape
+// tiles are ordered by groups of 4 tile columns, row by row within a group, so
+// the ~32 tiles an XCD runs at once form an 8x4 block that shares 8 row panels
+// and 4 column panels in that XCD's L2.
 #include "dpp_internal.h"
 
 namespace dpp {
@@ -36,41 +39,62 @@ namespace {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef const void __attribute__((address_space(1)))* gptr_t;
+typedef void __attribute__((address_space(3)))* lptr_t;
 
-constexpr int TM = 256;                       // tile rows (== tile cols)
-constexpr int KC = 32;                        // k per LDS stage
-constexpr int kThreads = 256;
-constexpr int kRowBytes = KC * 2;             // 64
-constexpr int kPlaneBytes = TM * kRowBytes;   // 16 KiB
-constexpr int kBufBytes = 4 * kPlaneBytes;    // Lh, Ll, Wh, Wl
-constexpr int kLdsBytes = 2 * kBufBytes;      // double buffered
+constexpr int KC = 32;             // k per LDS stage
+constexpr int kRowBytes = KC * 2;  // 64 bytes of bf16 per operand row and stage
+constexpr int kGroupCols = 4;      // tile columns per group of the wide order
 
-struct TileCoord {
-    int64_t i0, j0;
+template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_>
+struct Shape {
+    static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_;
+    static constexpr int MINB = MINB_;  // workgroups per CU the register budget allows
+    static constexpr int EP = EP_;      // 32x32 blocks per epilogue round
+    static constexpr int NW = WR * WC, THREADS = 64 * NW;
+    static constexpr int RB = TM / (32 * WR), CB = TN / (32 * WC);  // 32x32 blocks per wave
+    static constexpr int A_PLANE = TM * kRowBytes, W_PLANE = TN * kRowBytes;
+    static constexpr int BUF = 2 * A_PLANE + 2 * W_PLANE;           // Lh, Ll, Wh, Wl
+    static constexpr int LDS = 2 * BUF;
+    static constexpr int PER_WAVE = BUF / 1024 / NW;                // 1 KiB copies per stage
+    static constexpr int READS = 2 * (RB + CB);                     // fragments per k step
+    static constexpr int MFMAS = 3 * RB * CB;
+    static_assert(BUF % (1024 * NW) == 0, "copies must split evenly over wavefronts");
+    static_assert(MFMAS % READS == 0, "interleave needs whole MFMA groups per read");
 };
-
-__device__ __forceinline__ bool tile_of(int64_t t, int64_t NR, int64_t NC, bool herm,
-                                        TileCoord& tc)
-{
-    if (!herm) {
-        if (t >= NR * NC) return false;
-        tc.i0 = (t % NR) * TM;
-        tc.j0 = (t / NR) * TM;
-        return true;
-    }
-    int64_t J = 0, before = 0;
-    for (; J < NC; ++J) {
-        const int64_t here = NR - J;
-        if (t < before + here) break;
-        before += here;
-    }
-    if (J >= NC) return false;
-    tc.i0 = (J + (t - before)) * TM;
-    tc.j0 = J * TM;
-    return true;
-}
+using Wide = Shape<256, 256, 2, 2, 1, 2>;
+using Medium = Shape<256, 128, 2, 2, 1, 2>;
+using Narrow = Shape<128, 64, 4, 1, 3, 1>;
 
 __device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+
+constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format, gfx9 resource word 3
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ double buf_load_c(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load_c<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load_c<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store_c(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ void buf_store_c<double>(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store_c<float>(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, voff, soff, 0);
+}
 
 // Byte offset of logical 16-byte segment `seg` of row `r` inside a plane.
 __device__ __forceinline__ int lds_off(int r, int seg)
@@ -78,25 +102,63 @@ __device__ __forceinline__ int lds_off(int r, int seg)
     return r * kRowBytes + ((seg ^ swz(r)) << 4);
 }
 
-typedef const void __attribute__((address_space(1)))* gptr_t;
-typedef void __attribute__((address_space(3)))* lptr_t;
+struct TileCoord {
+    int64_t i0, j0;  // tile indices (row tile, column tile)
+};
 
-template <typename T, bool HERM>
-__global__ __launch_bounds__(kThreads, 1) void update_bf16x3(const DevProb* __restrict__ probs,
-                                                             int64_t base, int64_t ncols_req,
-                                                             int64_t k0, int kw, int64_t j0,
-                                                             int ss)
+// Grouped order over the tiles of the region (NR x NC tiles of equal size;
+// Hermitian: only J <= I). Groups of kGroupCols tile columns, row by row.
+__device__ __forceinline__ bool grouped_tile(int64_t t, int64_t NR, int64_t NC, bool herm,
+                                             TileCoord& tc)
+{
+    for (int64_t J0 = 0; J0 < NC; J0 += kGroupCols) {
+        const int64_t gw = NC - J0 < kGroupCols ? NC - J0 : kGroupCols;
+        const int64_t tri = herm ? gw * (gw - 1) / 2 : 0;
+        const int64_t rows = herm ? NR - (J0 + gw - 1) : NR;  // rows with all gw columns
+        const int64_t count = tri + (rows > 0 ? rows : 0) * gw;
+        if (t >= count) {
+            t -= count;
+            continue;
+        }
+        if (t < tri) {  // rows J0 .. J0+gw-2 hold 1 .. gw-1 tiles
+            int64_t i = 0;
+            while ((i + 1) * (i + 2) / 2 <= t) ++i;
+            tc.i0 = J0 + i;
+            tc.j0 = J0 + (t - i * (i + 1) / 2);
+        } else {
+            const int64_t p = t - tri;
+            tc.i0 = (herm ? J0 + gw - 1 : 0) + p / gw;
+            tc.j0 = J0 + p % gw;
+        }
+        return true;
+    }
+    return false;
+}
+
+template <typename T, bool HERM, class S>
+__global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevProb* __restrict__ probs,
+                                                               int64_t base, int64_t ncols_req,
+                                                               int64_t k0, int kw, int64_t j0,
+                                                               int ss)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
     const int64_t nrows = n - base;
     if (nrows <= 0 || k0 + kw > n) return;
     const int64_t ncols = ncols_req < nrows ? ncols_req : nrows;
-    const int64_t NR = (nrows + TM - 1) / TM, NC = (ncols + TM - 1) / TM;
+    const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (ncols + S::TN - 1) / S::TN;
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     TileCoord tc;
-    if (!tile_of(t, NR, NC, HERM, tc)) return;
+    if constexpr (S::TM == S::TN) {
+        if (!grouped_tile(t, NR, NC, HERM, tc)) return;
+    } else {
+        if (t >= NR * NC) return;
+        tc.i0 = t % NR;
+        tc.j0 = t / NR;
+        // Hermitian: skip tiles entirely above the diagonal.
+        if (HERM && (tc.i0 + 1) * S::TM <= tc.j0 * S::TN) return;
+    }
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
@@ -106,144 +168,231 @@ __global__ __launch_bounds__(kThreads, 1) void update_bf16x3(const DevProb* __re
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / S::WC, wc = wave % S::WC;
 
-    const int64_t rowT0 = base + tc.i0;
-    const int64_t colT0 = base + tc.j0;
+    const int64_t rowT0 = base + tc.i0 * S::TM;
+    const int64_t colT0 = base + tc.j0 * S::TN;
     const int64_t colEnd = base + ncols;
     const int kk0 = (int)(k0 - j0);
 
-    // Direct-to-LDS copies: wavefront `wave` fills plane `wave`. Instruction q
-    // (0..15) writes rows 16q .. 16q+15 of the plane; lane l supplies row
-    // 16q + l/4, physical segment l%4, i.e. logical segment (l%4) ^ swz(row);
-    // swz(16q + l/4) does not depend on q.
-    const int plane = wave;
-    const uint16_t* src_plane = split_plane(P.split, n, ss, plane);
-    const int64_t first = plane < 2 ? rowT0 : colT0;
-    const int64_t last = (plane < 2 ? n : colEnd) - 1;  // rows past it: reuse it
+    // Direct-to-LDS copies. Copy i of a stage writes bytes [1024 i, 1024 i + 1024)
+    // of the buffer (planes Lh, Ll, Wh, Wl back to back): 16 rows of one plane.
+    // Lane l supplies row 16q + l/4 of that block, physical segment l%4, i.e.
+    // logical segment (l%4) ^ swz(row); swz does not depend on q.
     const int rl = lane >> 2;
     const int seg8 = ((lane & 3) ^ swz(rl)) * 8;
     auto issue_stage = [&](int kc, int buf) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            int64_t g = first + 16 * q + rl;
+        for (int q = 0; q < S::PER_WAVE; ++q) {
+            const int i = wave * S::PER_WAVE + q;  // copy index, uniform
+            const int off = i * 1024;
+            int plane, row0;
+            if (off < 2 * S::A_PLANE) {
+                plane = off / S::A_PLANE;
+                row0 = (off % S::A_PLANE) / kRowBytes;
+            } else {
+                const int o2 = off - 2 * S::A_PLANE;
+                plane = 2 + o2 / S::W_PLANE;
+                row0 = (o2 % S::W_PLANE) / kRowBytes;
+            }
+            const int64_t first = plane < 2 ? rowT0 : colT0;
+            const int64_t last = (plane < 2 ? n : colEnd) - 1;  // rows past it: reuse it
+            int64_t g = first + row0 + rl;
             g = g < last ? g : last;
             __builtin_amdgcn_global_load_lds(
-                (gptr_t)(src_plane + g * ss + kk0 + kc + seg8),
-                (lptr_t)(lds + buf * kBufBytes + plane * kPlaneBytes + q * 1024), 16, 0, 0);
+                (gptr_t)(split_plane(P.split, n, ss, plane) + g * ss + kk0 + kc + seg8),
+                (lptr_t)(lds + buf * S::BUF + off), 16, 0, 0);
         }
     };
 
-    f16v acc[4][4];
+    f16v acc[S::RB][S::CB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < S::CB; ++cb)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.0f;
 
+    // Epilogue geometry (see the accumulator layout below): tile-relative row
+    // i, column j; stored iff i < rlim, j < clim and (lower part) i - j >= dd.
+    // Rounds r = (rb, pair of column blocks); each round is 32 values per lane.
+    const int rlim = (int)(n - rowT0);
+    const int clim = (int)(colEnd - colT0);
+    const int dd = (int)(colT0 - rowT0);
+    const int jl = wc * (S::TN / S::WC) + 4 * (lane >> 5);  // lane part of the column
+    constexpr int CP = S::EP;                                // column blocks per round
+    constexpr int ROUNDS = S::RB * (S::CB / CP);
+    auto c_ptr = [&](int rb) {
+        const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
+        return A + (rowT0 + i) + (colT0 + jl) * lda;
+    };
+    auto c_ok = [&](int rb, int ju) {
+        const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
+        const int j = jl + ju;
+        return i < rlim && j < clim && (!HERM || i - j >= dd);
+    };
+    // Interior tiles (fully inside the region and, for the lower part, fully
+    // below the diagonal) take a branch-free path: raw buffer loads and stores
+    // with one per-lane offset and a scalar per-column offset. Edge tiles use
+    // per-element predicates.
+    const bool interior = rlim >= S::TM && clim >= S::TN && (!HERM || -dd >= S::TN - 1);
+    const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
+        A + rowT0 + colT0 * lda, 0,
+        (int)(((int64_t)S::TN * lda) * (int64_t)sizeof(T) < 0x7fffffff
+                  ? ((int64_t)S::TN * lda) * (int64_t)sizeof(T) : 0x7fffffff),
+        kBufFlags);
+    auto c_voff = [&](int rb) {
+        const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
+        return (int)((i + (int64_t)jl * lda) * (int64_t)sizeof(T));
+    };
+    auto c_load = [&](int r, double (&cv)[CP][16]) {
+        const int rb = r / (S::CB / CP), c2 = (r % (S::CB / CP)) * CP;
+        if (interior) {
+            const int vo = c_voff(rb);
+#pragma unroll
+            for (int h = 0; h < CP; ++h)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
+                    cv[h][e] = buf_load_c<T>(crs, vo, (int)(ju * lda * (int64_t)sizeof(T)));
+                }
+            return;
+        }
+        T* const p0 = c_ptr(rb);
+#pragma unroll
+        for (int h = 0; h < CP; ++h)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
+                cv[h][e] = c_ok(rb, ju) ? (double)p0[ju * lda] : 0.0;
+            }
+    };
+    auto c_store = [&](int r, const double (&cv)[CP][16]) {
+        const int rb = r / (S::CB / CP), c2 = (r % (S::CB / CP)) * CP;
+        if (interior) {
+            const int vo = c_voff(rb);
+#pragma unroll
+            for (int h = 0; h < CP; ++h)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
+                    buf_store_c<T>(cv[h][e] - (double)acc[rb][c2 + h][e], crs, vo,
+                                   (int)(ju * lda * (int64_t)sizeof(T)));
+                }
+            return;
+        }
+        T* const p0 = c_ptr(rb);
+#pragma unroll
+        for (int h = 0; h < CP; ++h)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
+                if (c_ok(rb, ju)) p0[ju * lda] = (T)(cv[h][e] - (double)acc[rb][c2 + h][e]);
+            }
+    };
+
+    double cva[CP][16], cvb[CP][16];
     const int nstages = kw / KC;
     issue_stage(0, 0);
-    for (int s = 0; s < nstages; ++s) {
-        const int buf = s & 1;
-        // This wavefront's copies of stage s are in LDS; the barrier makes
+    for (int st = 0; st < nstages; ++st) {
+        const int buf = st & 1;
+        // This wavefront's copies of stage st are in LDS; the barrier makes
         // everyone's visible and retires every read of the other buffer.
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
-        if (s + 1 < nstages) issue_stage((s + 1) * KC, buf ^ 1);
-        const unsigned char* B0 = lds + buf * kBufBytes;
-        bf8 lh[2][4], ll[2][4], wh[2][4], wl[2][4];
+        if (st + 1 < nstages) issue_stage((st + 1) * KC, buf ^ 1);
+        else c_load(0, cva);  // first C round in flight during the last stage
+        const unsigned char* B0 = lds + buf * S::BUF;
+        bf8 lh[2][S::RB], ll[2][S::RB], wh[2][S::CB], wl[2][S::CB];
         auto read_frags = [&](int ks) {
             const int seg = ks * 2 + (lane >> 5);  // 8 k values per lane
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int ra = wr * 128 + b * 32 + (lane & 31);
-                const int rc = wc * 128 + b * 32 + (lane & 31);
-                lh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 0 * kPlaneBytes + lds_off(ra, seg)));
-                ll[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 1 * kPlaneBytes + lds_off(ra, seg)));
-                wh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * kPlaneBytes + lds_off(rc, seg)));
-                wl[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 3 * kPlaneBytes + lds_off(rc, seg)));
+            for (int b = 0; b < S::RB; ++b) {
+                const int ra = wr * (S::TM / S::WR) + b * 32 + (lane & 31);
+                lh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + lds_off(ra, seg)));
+                ll[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + S::A_PLANE + lds_off(ra, seg)));
+            }
+#pragma unroll
+            for (int b = 0; b < S::CB; ++b) {
+                const int rc = wc * (S::TN / S::WC) + b * 32 + (lane & 31);
+                wh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + lds_off(rc, seg)));
+                wl[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + S::W_PLANE + lds_off(rc, seg)));
             }
         };
+        // The three products of one accumulator are RB*CB MFMAs apart, so
+        // consecutive MFMAs never wait on each other's result.
         auto mfmas = [&](int ks) {
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int term = 0; term < 3; ++term)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[ks][cb], lh[ks][rb], acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl[ks][cb], lh[ks][rb], acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[ks][cb], ll[ks][rb], acc[rb][cb], 0, 0, 0);
-                }
+                for (int rb = 0; rb < S::RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < S::CB; ++cb) {
+                        const bf8& w = term == 1 ? wl[ks][cb] : wh[ks][cb];
+                        const bf8& l = term == 2 ? ll[ks][rb] : lh[ks][rb];
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, l, acc[rb][cb], 0, 0, 0);
+                    }
         };
         read_frags(0);
         read_frags(1);
         mfmas(0);
         mfmas(1);
-        // Schedule: k-step 0's 16 fragment reads, then its 48 MFMAs with
-        // k-step 1's 16 reads interleaved one per 3 MFMAs, then k-step 1's MFMAs.
-        __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);   // DS read
-        for (int i = 0; i < 16; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+        // Schedule: k step 0's fragment reads, then its MFMAs with k step 1's
+        // reads interleaved evenly, then k step 1's MFMAs.
+        __builtin_amdgcn_sched_group_barrier(0x100, S::READS, 0);            // DS read
+        for (int r = 0; r < S::READS; ++r) {
+            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS / S::READS, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                  // DS read
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, 48, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS, 0);
     }
 
     // Accumulator layout of the 32x32 MFMA with the column operand first:
     // element e of lane l is C row (l % 32), C column 8*(e/4) + 4*(l/32) + e%4
-    // of the 32x32 block. For each pair of blocks all 32 C values of a lane are
-    // loaded before any is stored: the stores could alias later loads, so
+    // of the 32x32 block. Each round's 32 C values of a lane are all loaded
+    // before any is stored: the stores could alias later loads, so
     // interleaving them would serialize one memory round trip per element.
-    // Tile-relative indices: row i, column j of the tile; stored iff
-    // i < rlim, j < clim and (lower part) i - j >= dd.
-    const int rlim = (int)(n - rowT0);
-    const int clim = (int)(colEnd - colT0);
-    const int dd = (int)(colT0 - rowT0);
-    const int jl = wc * 128 + 4 * (lane >> 5);  // lane part of the column
+    // Round r + 1 is loaded before round r is stored, so one round's latency
+    // overlaps the previous round's stores.
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-        const int i = wr * 128 + rb * 32 + (lane & 31);
-        T* const p0 = A + (rowT0 + i) + (colT0 + jl) * lda;
-#pragma unroll
-        for (int c2 = 0; c2 < 4; c2 += 2) {
-            double cv[2][16];
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);  // uniform part
-                    const int j = jl + ju;
-                    const bool ok = i < rlim && j < clim && (!HERM || i - j >= dd);
-                    cv[h][e] = ok ? (double)p0[ju * lda] : 0.0;
-                }
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
-                    const int j = jl + ju;
-                    const bool ok = i < rlim && j < clim && (!HERM || i - j >= dd);
-                    if (ok) p0[ju * lda] = (T)(cv[h][e] - (double)acc[rb][c2 + h][e]);
-                }
-        }
+    for (int r = 0; r < ROUNDS; ++r) {
+        double (&cur)[CP][16] = (r & 1) ? cvb : cva;
+        double (&nxt)[CP][16] = (r & 1) ? cva : cvb;
+        if (r + 1 < ROUNDS) c_load(r + 1, nxt);
+        c_store(r, cur);
     }
 }
 
-template <typename T, bool HERM>
-hipError_t launch_t(const DevProb* probs, int nprob, unsigned grid_x, int64_t base, int64_t ncols,
-                    int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
+template <typename T, bool HERM, class S>
+hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, int64_t base,
+                        int64_t ncols, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
-    auto k = update_bf16x3<T, HERM>;
+    const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (nc + S::TN - 1) / S::TN;
+    const int64_t tiles = (HERM && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
+    const unsigned grid_x = (unsigned)((tiles + 7) / 8 * 8);  // XCD remap needs a multiple of 8
+    auto k = update_bf16x3<T, HERM, S>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k, dim3(grid_x, nprob), dim3(kThreads), kLdsBytes, s, probs, base, ncols,
+    hipLaunchKernelGGL(k, dim3(grid_x, nprob), dim3(S::THREADS), S::LDS, s, probs, base, ncols,
                        k0, kw, j0, ss);
     return hipGetLastError();
+}
+
+template <typename T, bool HERM>
+hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, int64_t base,
+                    int64_t ncols, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
+{
+    // The tile shape follows the width of the updated column range.
+    if (nc <= 128)
+        return launch_shape<T, HERM, Narrow>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+    if (nc <= 256)
+        return launch_shape<T, HERM, Medium>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+    return launch_shape<T, HERM, Wide>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
 }
 
 }  // namespace
@@ -256,15 +405,12 @@ hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int 
     if (nrows <= 0) return hipSuccess;
     if (kw % KC != 0) return hipErrorInvalidValue;
     const int64_t nc = ncols < nrows ? ncols : nrows;
-    const int64_t NR = (nrows + TM - 1) / TM, NC = (nc + TM - 1) / TM;
-    const int64_t tiles = herm ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
-    const unsigned grid_x = (unsigned)((tiles + 7) / 8 * 8);  // XCD remap needs a multiple of 8
     if (herm) {
-        if (dtype == 0) return launch_t<double, true>(probs, nprob, grid_x, base, ncols, k0, kw, j0, ss, s);
-        return launch_t<float, true>(probs, nprob, grid_x, base, ncols, k0, kw, j0, ss, s);
+        if (dtype == 0) return launch_t<double, true>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+        return launch_t<float, true>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
     }
-    if (dtype == 0) return launch_t<double, false>(probs, nprob, grid_x, base, ncols, k0, kw, j0, ss, s);
-    return launch_t<float, false>(probs, nprob, grid_x, base, ncols, k0, kw, j0, ss, s);
+    if (dtype == 0) return launch_t<double, false>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+    return launch_t<float, false>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
 }
 
 }  // namespace dpp
