@@ -92,6 +92,24 @@ def run_path(torch, B, K, us, prec, args, As, ws):
     }
 
 
+def measured_traffic(name, n, batch):
+    """HBM bytes per launch of `name` from the committed counter record
+    (profiles/<name>_n<n>_traffic.json: FETCH_SIZE and WRITE_SIZE passes scaled
+    by a copy of known size), or None if there is none for this workload or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{name}_n{n}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    if f"{batch} samples per batched call" not in rec["workload"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def roofline_entry(prof, name, peak):
     k = prof.get(name)
     if not k or k["ms"] <= 0:
@@ -204,6 +222,8 @@ def main():
     dom = "update_bf16x3" if order[0] == "split" else "update_f64"
     out["roofline"] = roofline_entry(head["profile"], dom,
                                      PEAK_BF16 if order[0] == "split" else PEAK_FP64)
+    if out["roofline"] is not None:
+        out["roofline"]["traffic"] = measured_traffic(dom, n, bsz)
     if "fp64" in res and order[0] != "fp64":
         out["roofline_fp64"] = roofline_entry(res["fp64"]["profile"], "update_f64", PEAK_FP64)
 
