@@ -49,44 +49,82 @@ def parse():
                         "(lets profiled runs skip the QR of the generator)")
     p.add_argument("--prepare-only", action="store_true",
                    help="generate (and cache) K, then exit")
+    p.add_argument("--no-graph", action="store_true",
+                   help="launch every step eagerly instead of replaying a captured HIP graph")
     return p.parse_args()
 
 
 def run_path(torch, B, K, us, prec, args, As, ws):
-    """Warm up, then time `args.steps` steps; returns timing and profile."""
+    """Warm up, then time `args.steps` steps; returns timing and profile.
+
+    A step restores each sample's working copy from K and runs one batched
+    call. By default one step is captured in a HIP graph and the timed steps
+    replay it (the launch list of a call depends only on the sizes, so every
+    replay does the full work on the same buffers); the per-kernel event
+    profile then comes from one eager step after the timed region."""
     n = K.shape[0]
+    dev = K.device
+    outs = [{"mask": torch.empty(n, dtype=torch.uint8, device=dev),
+             "pivots": torch.empty(n, dtype=torch.float64, device=dev),
+             "loglik": torch.empty(1, dtype=torch.float64, device=dev),
+             "info": torch.empty(1, dtype=torch.int32, device=dev)} for _ in As]
 
     def step():
         for A in As:
             A.copy_(K)
-        return B.dpp_sample_ldlh_batched([A.t() for A in As], us, prec=prec, ws=ws)
+        B.dpp_sample_ldlh_batched([A.t() for A in As], us, prec=prec, ws=ws, outs=outs)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    B.dpp_profile_begin()
+    graph = None
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+    else:
+        B.dpp_profile_begin()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    outs = None
     for _ in range(args.steps):
-        outs = step()
+        if graph is not None:
+            graph.replay()
+        else:
+            step()
     ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = B.dpp_profile_end()
-    wall_ms = (t1 - t0) * 1e3
-    samples = args.steps * len(As)
     sizes = [int(o["mask"].sum().item()) for o in outs]
     infos = [int(o["info"].item()) for o in outs]
+    if graph is not None:
+        B.dpp_profile_begin()
+        step()
+        prof = B.dpp_profile_end()
+        prof_samples = len(As)
+        sizes += [int(o["mask"].sum().item()) for o in outs]
+        infos += [int(o["info"].item()) for o in outs]
+        del graph
+    else:
+        prof = B.dpp_profile_end()
+        prof_samples = args.steps * len(As)
+    wall_ms = (t1 - t0) * 1e3
+    samples = args.steps * len(As)
     lib_ms = sum(v["ms"] for v in prof.values())
     flops_per_sample = n ** 3 / 3.0
     return {
         "ms_per_step": wall_ms / args.steps,
         "samples_per_s": samples / (wall_ms * 1e-3),
         "tflops": samples * flops_per_sample / (wall_ms * 1e-3) / 1e12,
-        "kernel_ms_per_sample": lib_ms / samples,
+        "kernel_ms_per_sample": lib_ms / prof_samples,
         "sizes": sizes, "infos": infos, "profile": prof,
         "event_ms": ev0.elapsed_time(ev1),
     }
@@ -95,17 +133,18 @@ def run_path(torch, B, K, us, prec, args, As, ws):
 def measured_traffic(name, n, batch):
     """HBM bytes per launch of `name` from the committed counter record
     (profiles/<name>_n<n>_traffic.json: FETCH_SIZE and WRITE_SIZE passes scaled
-    by a copy of known size), or None if there is none for this workload or the
-    kernel source changed since the counters were taken."""
+    by a copy of known size), or None if there is none for this workload or if
+    the kernel source or the launch sequence changed since the counters were
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{name}_n{n}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, rec["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-        return None
-    if f"{batch} samples per batched call" not in rec["workload"]:
+    for src, sha in rec.get("sources", {}).items():
+        if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != sha:
+            return None
+    if not rec.get("sources") or f"{batch} samples per batched call" not in rec["workload"]:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -201,7 +240,8 @@ def main():
                                f"LDL^H sampler, {bsz} samples per step (one batched call), "
                                f"working copy restored from K inside each step",
                    "n": n, "rank": r, "batch": bsz,
-                   "precision": "split_bf16x3" if order[0] == "split" else "fp64"},
+                   "precision": "split_bf16x3" if order[0] == "split" else "fp64",
+                   "launch": "eager" if args.no_graph else "HIP graph replay of one step"},
         "tflops": round(head["tflops"], 3),
     }
     for name in order:

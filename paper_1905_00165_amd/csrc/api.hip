@@ -4,7 +4,7 @@
 // Launch sequence (blocked right-looking sampler, Sec. 3; the unblocked
 // sampler of Sec. 2 on each 64-wide diagonal block):
 //
-//   LDL^H, outer block width B0 (FP64: 256, split-BF16: 1024):
+//   LDL^H, outer block width B0 (FP64: 256, split-BF16: 2048):
 //     for each outer panel [j0, j1):
 //       factor_panel(j0, j1)                       -- recursive, below
 //       update rows/cols [j1, n) by columns [j0, j1) -- the trailing update
@@ -50,7 +50,7 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec)
     // Outer panel width: each trailing update reads and writes the trailing
     // matrix once, so its HBM traffic per sample is ~ 8 n^3 / (3 B0) bytes for
     // FP64 storage; the split path needs the wider panel to stay MFMA-bound.
-    if (herm) p.B0 = p.split ? 1024 : 256;
+    if (herm) p.B0 = p.split ? 2048 : 256;
     else p.B0 = kLeaf;
     p.ss = p.B0;
     return p;

@@ -85,6 +85,15 @@ __device__ __forceinline__ void buf_store<float>(double v, __amdgpu_buffer_rsrc_
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, voff, soff, 0);
 }
 
+// hi/lo BF16 split of one value: hi = bf16(x), lo = bf16(x - hi), so that
+// hi + lo carries about 16 significant bits of x.
+__device__ __forceinline__ void split_bf16(double x, uint16_t& hi, uint16_t& lo)
+{
+    const uint32_t xh = bf16_bits((float)x);
+    hi = (uint16_t)xh;
+    lo = (uint16_t)bf16_bits((float)(x - (double)bf16_value(xh)));
+}
+
 // Write the hi/lo BF16 split of v[0..63] to two rows (64 bf16 each, 16-byte
 // aligned), as 8 stores of 16 bytes per row.
 __device__ __forceinline__ void store_split_row(uint16_t* hi_row, uint16_t* lo_row,

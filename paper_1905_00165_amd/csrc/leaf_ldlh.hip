@@ -1,4 +1,5 @@
-// Diagonal-block kernel, Hermitian (LDL^H) form; see leaf_common.h.
+// Diagonal-block kernel, Hermitian (LDL^H) form; see leaf_common.h for the
+// chain. The panel solve below the block runs on the matrix cores.
 #include "leaf_common.h"
 
 namespace dpp {
@@ -6,24 +7,59 @@ namespace {
 
 using namespace leaf;
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;                   // wavefronts per workgroup
+constexpr int kGroups = 4;                  // 16-row groups per wavefront
+constexpr int kRows = kWaves * kGroups * 16;  // panel rows per workgroup
+constexpr int kThreads = kWaves * 64;
+constexpr int kTilePitch = 66;              // doubles per row of a staged 16 x 64 tile
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // ------------------------------------------------------------------- LDL^H
+// Step 1 (wavefront 0, every workgroup): the unblocked sampler on the 64x64
+// diagonal block, one block row per lane; see leaf_common.h.
+//
+// Step 2: the panel rows below the block. With W = A21 L11^{-T} (the unscaled
+// columns, W = L21 D1) and the 64 columns cut into four 16-column blocks,
+//   W_b = (A_b - sum_{c<b} W_c L_bc^T) L_bb^{-T},    b = 0..3,
+// or, transposed, W_b^T = L_bb^{-1} (A_b^T - sum_{c<b} L_bc W_c^T). Each
+// product has a 16x16 block of L11 (or the inverse of a diagonal block) on the
+// left and the 16 rows of a row group on the right. v_mfma_f64_16x16x4f64
+// leaves output element e of lane l at row l/16 + 4e, column l%16, and takes
+// its right-hand operand for 4-deep slab s as row l/16, column l%16 of that
+// slab -- so output element e = s of one product is, lane for lane, slab s of
+// the right-hand operand of the next, and a row group never leaves registers.
+// The four inverses L_bb^{-1} (unit lower triangular) are formed once per
+// workgroup by forward substitution, one column per lane.
+// Then L21 = W D1^{-1}; A receives L21, the split planes W and L21.
 template <typename T, bool SPLIT>
-__global__ __launch_bounds__(kRowsPerWG) void leaf_ldlh(const DevProb* __restrict__ probs, int64_t c0,
-                                                 int64_t j0, int ss)
+__global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restrict__ probs, int64_t c0,
+                                               int64_t j0, int ss)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
     if (c0 >= n) return;
     const int bs = (int)((n - c0) < L ? (n - c0) : L);
-    const int64_t row0 = c0 + bs + (int64_t)blockIdx.x * kRowsPerWG;
+    const int64_t row0 = c0 + bs + (int64_t)blockIdx.x * kRows;
     if (blockIdx.x > 0 && row0 >= n) return;
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
 
-    __shared__ double sL[L * L];  // sL[t*L + k] = L11[k][t] (column t), zero elsewhere
-    __shared__ double sD[L];      // D1 (modified pivots)
-    __shared__ double sB[L];      // broadcast column of the current pivot
+    // One LDS array carved by hand so that sB sits at address 0: the chain's
+    // 64-entry broadcast reads then all use one base register and immediate
+    // offsets.
+    __shared__ double smem[2 * L + L * L + 4 * 16 * 16 + kWaves * 16 * kTilePitch];
+    double* const sB = smem;               // broadcast column of the current pivot
+    double* const sR = smem + L;           // 1 / D1
+    double* const sL = smem + 2 * L;       // sL[t*L + k] = L11[k][t] for k > t, zero elsewhere
+    double* const sI = sL + L * L;         // sI[b*256 + i*16 + k] = (L_bb^{-1})[i][k]
+    double* const sT = sI + 4 * 16 * 16;   // per wavefront: W of one row group, row-major
 
     const int tid = threadIdx.x;
     if (tid < L) {
@@ -31,15 +67,30 @@ __global__ __launch_bounds__(kRowsPerWG) void leaf_ldlh(const DevProb* __restric
         // Row `lane` of the block, lower part; the rest starts at 0 and only
         // ever receives finite garbage that no decision reads.
         double a[L];
+        {
+            // Buffer loads: the column offset is a scalar, so the 64 loads
+            // share one address register; reads past the end of A return 0.
+            const int64_t base = c0 + c0 * lda;
+            const __amdgpu_buffer_rsrc_t rb =
+                strip_rsrc(A + base, ((n - 1) * lda + n - base) * (int64_t)sizeof(T));
+            const int cs = (int)(lda * (int64_t)sizeof(T));
 #pragma unroll
-        for (int k = 0; k < L; ++k)
-            a[k] = (lane < bs && k <= lane) ? (double)A[(c0 + lane) + (c0 + k) * lda] : 0.0;
+            for (int k = 0; k < L; ++k) {
+                const double v = buf_load<T>(rb, lane * (int)sizeof(T), k * cs);
+                a[k] = (lane < bs && k <= lane) ? v : 0.0;
+            }
+        }
         const double ul = lane < bs ? P.u[c0 + lane] : 2.0;
         double mydp = 1.0;
         int mykeep = 0;
+        int me = lane;
 
 #pragma unroll
         for (int j = 0; j < L; ++j) {
+            // Keeps the compiler from hoisting the 64 per-step lane masks
+            // (lane == j, lane > j) out of the unrolled loop, where they
+            // would occupy 128 scalar registers and spill.
+            asm volatile("" : "+v"(me));
             if (j < bs) {
                 const double d = readlane_d(a[j], j);   // A[j][j]
                 const double uj = readlane_d(ul, j);
@@ -53,19 +104,16 @@ __global__ __launch_bounds__(kRowsPerWG) void leaf_ldlh(const DevProb* __restric
                 for (int k = 0; k < L; ++k)
                     if (k > j) a[k] -= l * sB[k];  // A[lane][k] -= l_lane * A[k][j]
                 __builtin_amdgcn_wave_barrier();
-                if (lane == j) {
-                    a[j] = dp;
-                    mydp = dp;
-                    mykeep = keep ? 1 : 0;
-                } else if (lane > j) {
-                    a[j] = l;
-                }
+                const bool isj = me == j;
+                a[j] = isj ? dp : (me > j ? l : c);
+                mydp = isj ? dp : mydp;
+                mykeep = isj ? (keep ? 1 : 0) : mykeep;
             }
         }
 
 #pragma unroll
         for (int k = 0; k < L; ++k) sL[k * L + lane] = (k < lane && lane < bs) ? a[k] : 0.0;
-        sD[lane] = (lane < bs) ? mydp : 1.0;
+        sR[lane] = (lane < bs) ? 1.0 / mydp : 1.0;
 
         // The factored block goes to the workspace strip, not to A: other
         // workgroups of this launch may still be loading the original block
@@ -80,43 +128,126 @@ __global__ __launch_bounds__(kRowsPerWG) void leaf_ldlh(const DevProb* __restric
         }
     }
     __syncthreads();
+    // Rows below a block exist only when the block is a full 64 wide (a
+    // ragged block is the last one), so bs == L from here on.
+    if (row0 >= n) return;
 
-    // Panel solve: row r of A21 becomes W = A21 L11^{-T} (= L21 D1), then
-    // L21 = W D1^{-1}. Rows below a block exist only when the block is a full
-    // 64 wide (a ragged block is the last one), so bs == L here.
-    const int64_t r = row0 + tid;
-    if (r < n) {
-        // Strip = columns [c0, c0+64) from row row0 on; lane offset tid rows,
-        // column k at k * lda elements.
-        const __amdgpu_buffer_rsrc_t rs =
-            strip_rsrc(A + row0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
-        const int voff = tid * (int)sizeof(T);
-        const int cstride = (int)(lda * (int64_t)sizeof(T));
-        double x[L];
+    if (tid < 64) {
+        // Column c of L_bb^{-1}: solve L_bb y = e_c by forward substitution.
+        const int b = tid >> 4, c = tid & 15;
+        double y[16];
 #pragma unroll
-        for (int k = 0; k < L; ++k) x[k] = buf_load<T>(rs, voff, k * cstride);
+        for (int k = 0; k < 16; ++k) {
+            double acc = (k == c) ? 1.0 : 0.0;
 #pragma unroll
-        for (int t = 0; t < L; ++t) {
-            const double wt = x[t];
-#pragma unroll
-            for (int k = 0; k < L; ++k)
-                if (k > t) x[k] -= wt * sL[t * L + k];
+            for (int t = 0; t < k; ++t) acc -= sL[(16 * b + t) * L + 16 * b + k] * y[t];
+            y[k] = acc;
         }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sI[b * 256 + k * 16 + c] = y[k];
+    }
+    __syncthreads();
+
+    const int lane = tid & 63;
+    const int q = lane >> 4, i16 = lane & 15;
+    const int64_t wrow0 = row0 + (int64_t)(tid >> 6) * (kGroups * 16);
+    if (wrow0 >= n) return;
+
+    // Left-hand operands, slab s: lane holds [row i16][column 4s + q] of
+    // -L_bc (c < b) or of L_bb^{-1}; read from LDS for every row group.
+    auto frag_o = [&](int b, int c, int s) { return -sL[(16 * c + 4 * s + q) * L + 16 * b + i16]; };
+    auto frag_i = [&](int b, int s) { return sI[b * 256 + i16 * 16 + 4 * s + q]; };
+
+    // Strip = columns [c0, c0+64) from row wrow0 on; lane (q, i16) of group g
+    // reads row wrow0 + 16g + i16 of columns q + 4e + 16b.
+    const __amdgpu_buffer_rsrc_t rs =
+        strip_rsrc(A + wrow0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
+    const int cstride = (int)(lda * (int64_t)sizeof(T));
+    const int ngroups = (int)((n - wrow0 + 15) / 16) < kGroups ? (int)((n - wrow0 + 15) / 16) : kGroups;
+
+    auto voff_of = [&](int g) {
+        const int64_t r = wrow0 + 16 * g + i16;
+        const int rr = (int)((r < n ? r : n - 1) - wrow0);  // tail rows re-read the last row
+        return rr * (int)sizeof(T) + q * cstride;
+    };
+    double nxt[16];
+    {
+        const int v = voff_of(0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+    }
+    for (int g = 0; g < ngroups; ++g) {
+        double cur[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+        if (g + 1 < ngroups) {
+            const int v = voff_of(g + 1);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+        }
+        d4 x[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            d4 acc = {cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3]};
+#pragma unroll
+            for (int c = 0; c < b; ++c)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = mfma16(frag_o(b, c, s), x[c][s], acc);
+            d4 xb = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) xb = mfma16(frag_i(b, s), acc[s], xb);
+            x[b] = xb;
+        }
+        // x[b][e] = W[row][16b + 4e + q], row = wrow0 + 16g + i16.
+        const int64_t r = wrow0 + 16 * g + i16;
         if constexpr (SPLIT) {
-            // W = L21 D1 first, then x becomes L21 in place.
-            const int64_t off = r * ss + (int)(c0 - j0);
-            store_split_row(split_plane(P.split, n, ss, 2) + off,
-                            split_plane(P.split, n, ss, 3) + off, x, L);
-        }
+            // The split planes are row-major: stage W through LDS so that each
+            // lane writes 16-byte pieces of one row (lane l: row l/4, columns
+            // 8(l%4) + [0, 8) and 32 + 8(l%4) + [0, 8)).
+            double* const tile = sT + (tid >> 6) * (16 * kTilePitch);
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            x[k] = x[k] / sD[k];
-            buf_store<T>(x[k], rs, voff, k * cstride);
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) tile[i16 * kTilePitch + 16 * b + 4 * e + q] = x[b][e];
+            __builtin_amdgcn_wave_barrier();
+            const int tr = lane >> 2, tc = 8 * (lane & 3);
+            const int64_t rr = wrow0 + 16 * g + tr;
+            if (rr < n) {
+                const int64_t off = rr * ss + (int)(c0 - j0) + tc;
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    uint32_t wh[4], wl[4], lh[4], ll[4];
+#pragma unroll
+                    for (int p2 = 0; p2 < 4; ++p2) {
+                        uint16_t h0, l0, h1, l1, a0, b0, a1, b1;
+                        const int col = 32 * half + tc + 2 * p2;
+                        const double w0 = tile[tr * kTilePitch + col];
+                        const double w1 = tile[tr * kTilePitch + col + 1];
+                        split_bf16(w0, h0, l0);
+                        split_bf16(w1, h1, l1);
+                        split_bf16(w0 * sR[col], a0, b0);
+                        split_bf16(w1 * sR[col + 1], a1, b1);
+                        wh[p2] = h0 | ((uint32_t)h1 << 16);
+                        wl[p2] = l0 | ((uint32_t)l1 << 16);
+                        lh[p2] = a0 | ((uint32_t)a1 << 16);
+                        ll[p2] = b0 | ((uint32_t)b1 << 16);
+                    }
+                    const int64_t o = off + 32 * half;
+                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 2) + o) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 3) + o) = make_uint4(wl[0], wl[1], wl[2], wl[3]);
+                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 0) + o) = make_uint4(lh[0], lh[1], lh[2], lh[3]);
+                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 1) + o) = make_uint4(ll[0], ll[1], ll[2], ll[3]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        if constexpr (SPLIT) {
-            const int64_t off = r * ss + (int)(c0 - j0);
-            store_split_row(split_plane(P.split, n, ss, 0) + off,
-                            split_plane(P.split, n, ss, 1) + off, x, L);
+        if (r < n) {
+            const int v = voff_of(g);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    buf_store<T>(x[b][e] * sR[16 * b + 4 * e + q], rs, v, (16 * b + 4 * e) * cstride);
         }
     }
 }
@@ -126,8 +257,8 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
                     int64_t j0, int ss, hipStream_t s)
 {
     const int64_t below = nmax - c0 - L;
-    const int gx = below > 0 ? (int)((below + kRowsPerWG - 1) / kRowsPerWG) : 1;
-    dim3 grid(gx, nprob), block(kRowsPerWG);
+    const int gx = below > 0 ? (int)((below + kRows - 1) / kRows) : 1;
+    dim3 grid(gx, nprob), block(kThreads);
     if (split) hipLaunchKernelGGL((leaf_ldlh<T, true>), grid, block, 0, s, probs, c0, j0, ss);
     else hipLaunchKernelGGL((leaf_ldlh<T, false>), grid, block, 0, s, probs, c0, j0, ss);
     return hipGetLastError();

@@ -42,31 +42,63 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef const void __attribute__((address_space(1)))* gptr_t;
 typedef void __attribute__((address_space(3)))* lptr_t;
 
-constexpr int KC = 32;             // k per LDS stage
-constexpr int kRowBytes = KC * 2;  // 64 bytes of bf16 per operand row and stage
+constexpr int kKAlign = 32;        // every update's k range is a multiple of this
 constexpr int kGroupCols = 4;      // tile columns per group of the wide order
 
-template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_>
+// TM x TN tile on WR x WC wavefronts; K advances KC at a time through NST LDS
+// stages (NST - 1 of them in flight while one is multiplied).
+template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_, int KC_, int NST_>
 struct Shape {
     static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_;
     static constexpr int MINB = MINB_;  // workgroups per CU the register budget allows
     static constexpr int EP = EP_;      // 32x32 blocks per epilogue round
+    static constexpr int KC = KC_, NST = NST_;
+    static constexpr int ROWB = KC * 2;                            // bytes per operand row and stage
+    static constexpr int KSTEPS = KC / 16;                         // MFMA k steps per stage
     static constexpr int NW = WR * WC, THREADS = 64 * NW;
     static constexpr int RB = TM / (32 * WR), CB = TN / (32 * WC);  // 32x32 blocks per wave
-    static constexpr int A_PLANE = TM * kRowBytes, W_PLANE = TN * kRowBytes;
+    static constexpr int A_PLANE = TM * ROWB, W_PLANE = TN * ROWB;
     static constexpr int BUF = 2 * A_PLANE + 2 * W_PLANE;           // Lh, Ll, Wh, Wl
-    static constexpr int LDS = 2 * BUF;
+    static constexpr int LDS = NST * BUF;
     static constexpr int PER_WAVE = BUF / 1024 / NW;                // 1 KiB copies per stage
+    static constexpr int LPR = ROWB / 16;                           // lanes per row in a copy
     static constexpr int READS = 2 * (RB + CB);                     // fragments per k step
     static constexpr int MFMAS = 3 * RB * CB;
+    static_assert(KC == 16 || KC == 32, "rows of 32 or 64 bytes");
+    static_assert(kKAlign % KC == 0, "stages must tile every k range");
     static_assert(BUF % (1024 * NW) == 0, "copies must split evenly over wavefronts");
     static_assert(MFMAS % READS == 0, "interleave needs whole MFMA groups per read");
+    static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
 };
-using Wide = Shape<256, 256, 2, 2, 1, 2>;
-using Medium = Shape<256, 128, 2, 2, 1, 2>;
-using Narrow = Shape<128, 64, 4, 1, 3, 1>;
+using Wide = Shape<256, 256, 2, 2, 1, 2, 32, 2>;
+using Medium = Shape<256, 128, 2, 2, 1, 2, 32, 2>;
+using Narrow = Shape<128, 64, 4, 1, 3, 1, 32, 2>;
 
-__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+// XOR swizzle of the 16-byte segments of LDS row r, so that the fragment
+// reads of consecutive rows spread over the banks: 64-byte rows (four
+// segments) flip by bits 1-2 of the row, 32-byte rows (two) by bit 2.
+template <int ROWB>
+__device__ __forceinline__ int swz(int r)
+{
+    return ROWB == 64 ? (r >> 1) & 3 : (r >> 2) & 1;
+}
+
+// s_waitcnt immediate that waits until at most n vector-memory loads of this
+// wavefront are outstanding (expcnt and lgkmcnt left alone).
+__device__ __forceinline__ void wait_vmcnt_le(int n)
+{
+    switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+    case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+    case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
+    case 16: __builtin_amdgcn_s_waitcnt(0x4F70); break;
+    case 24: __builtin_amdgcn_s_waitcnt(0x4F78); break;
+    case 32: __builtin_amdgcn_s_waitcnt(0x8F70); break;
+    default: __builtin_amdgcn_s_waitcnt(0x0F70); break;  // vmcnt(0): always safe
+    }
+}
 
 constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format, gfx9 resource word 3
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -97,9 +129,10 @@ __device__ __forceinline__ void buf_store_c<float>(double v, __amdgpu_buffer_rsr
 }
 
 // Byte offset of logical 16-byte segment `seg` of row `r` inside a plane.
+template <int ROWB>
 __device__ __forceinline__ int lds_off(int r, int seg)
 {
-    return r * kRowBytes + ((seg ^ swz(r)) << 4);
+    return r * ROWB + ((seg ^ swz<ROWB>(r)) << 4);
 }
 
 struct TileCoord {
@@ -176,11 +209,12 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     const int kk0 = (int)(k0 - j0);
 
     // Direct-to-LDS copies. Copy i of a stage writes bytes [1024 i, 1024 i + 1024)
-    // of the buffer (planes Lh, Ll, Wh, Wl back to back): 16 rows of one plane.
-    // Lane l supplies row 16q + l/4 of that block, physical segment l%4, i.e.
-    // logical segment (l%4) ^ swz(row); swz does not depend on q.
-    const int rl = lane >> 2;
-    const int seg8 = ((lane & 3) ^ swz(rl)) * 8;
+    // of the buffer (planes Lh, Ll, Wh, Wl back to back): 1024 / ROWB rows of
+    // one plane. Lane l supplies row l / LPR of that block, physical segment
+    // l % LPR, i.e. logical segment (l % LPR) ^ swz(row); the block starts at a
+    // multiple of 16 rows, so swz depends on l only.
+    const int rl = lane / S::LPR;
+    const int seg8 = ((lane % S::LPR) ^ swz<S::ROWB>(rl)) * 8;
     auto issue_stage = [&](int kc, int buf) {
 #pragma unroll
         for (int q = 0; q < S::PER_WAVE; ++q) {
@@ -189,11 +223,11 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
             int plane, row0;
             if (off < 2 * S::A_PLANE) {
                 plane = off / S::A_PLANE;
-                row0 = (off % S::A_PLANE) / kRowBytes;
+                row0 = (off % S::A_PLANE) / S::ROWB;
             } else {
                 const int o2 = off - 2 * S::A_PLANE;
                 plane = 2 + o2 / S::W_PLANE;
-                row0 = (o2 % S::W_PLANE) / kRowBytes;
+                row0 = (o2 % S::W_PLANE) / S::ROWB;
             }
             const int64_t first = plane < 2 ? rowT0 : colT0;
             const int64_t last = (plane < 2 ? n : colEnd) - 1;  // rows past it: reuse it
@@ -292,31 +326,49 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     };
 
     double cva[CP][16], cvb[CP][16];
-    const int nstages = kw / KC;
-    issue_stage(0, 0);
+    const int nstages = kw / S::KC;
+    for (int p = 0; p < S::NST - 1; ++p)
+        if (p < nstages) issue_stage(p * S::KC, p);
     for (int st = 0; st < nstages; ++st) {
-        const int buf = st & 1;
-        // This wavefront's copies of stage st are in LDS; the barrier makes
-        // everyone's visible and retires every read of the other buffer.
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-        __syncthreads();
-        if (st + 1 < nstages) issue_stage((st + 1) * KC, buf ^ 1);
-        else c_load(0, cva);  // first C round in flight during the last stage
+        const int buf = st % S::NST;
+        // This wavefront's copies of stage st are in LDS (the later stages
+        // already issued may still be in flight); the barrier makes everyone's
+        // visible and retires every read of the buffer refilled next.
+        const int later = nstages - 1 - st < S::NST - 2 ? nstages - 1 - st : S::NST - 2;
+        wait_vmcnt_le(later * S::PER_WAVE);
+        // A bare s_barrier: __syncthreads() would add a release fence, i.e.
+        // vmcnt(0), and drain the stages still in flight. Ordering needs no
+        // fence here: each wavefront has waited for its own copies of this
+        // stage, and its reads of the buffer refilled below returned before
+        // the MFMAs that consumed them. The memory clobber keeps the compiler
+        // from moving LDS accesses across the barrier.
+        asm volatile("s_barrier" ::: "memory");
+        if (st + S::NST - 1 < nstages) issue_stage((st + S::NST - 1) * S::KC, (st + S::NST - 1) % S::NST);
+        else if (st == nstages - 1) c_load(0, cva);  // first C round in flight during the last stage
         const unsigned char* B0 = lds + buf * S::BUF;
-        bf8 lh[2][S::RB], ll[2][S::RB], wh[2][S::CB], wl[2][S::CB];
+        bf8 lh[S::KSTEPS][S::RB], ll[S::KSTEPS][S::RB], wh[S::KSTEPS][S::CB], wl[S::KSTEPS][S::CB];
+        // Fragments in the order the MFMAs below consume them.
         auto read_frags = [&](int ks) {
             const int seg = ks * 2 + (lane >> 5);  // 8 k values per lane
 #pragma unroll
             for (int b = 0; b < S::RB; ++b) {
                 const int ra = wr * (S::TM / S::WR) + b * 32 + (lane & 31);
-                lh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + lds_off(ra, seg)));
-                ll[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + S::A_PLANE + lds_off(ra, seg)));
+                lh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + lds_off<S::ROWB>(ra, seg)));
             }
 #pragma unroll
             for (int b = 0; b < S::CB; ++b) {
                 const int rc = wc * (S::TN / S::WC) + b * 32 + (lane & 31);
-                wh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + lds_off(rc, seg)));
-                wl[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + S::W_PLANE + lds_off(rc, seg)));
+                wh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + lds_off<S::ROWB>(rc, seg)));
+            }
+#pragma unroll
+            for (int b = 0; b < S::CB; ++b) {
+                const int rc = wc * (S::TN / S::WC) + b * 32 + (lane & 31);
+                wl[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + S::W_PLANE + lds_off<S::ROWB>(rc, seg)));
+            }
+#pragma unroll
+            for (int b = 0; b < S::RB; ++b) {
+                const int ra = wr * (S::TM / S::WR) + b * 32 + (lane & 31);
+                ll[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + S::A_PLANE + lds_off<S::ROWB>(ra, seg)));
             }
         };
         // The three products of one accumulator are RB*CB MFMAs apart, so
@@ -333,18 +385,32 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, l, acc[rb][cb], 0, 0, 0);
                     }
         };
-        read_frags(0);
-        read_frags(1);
-        mfmas(0);
-        mfmas(1);
-        // Schedule: k step 0's fragment reads, then its MFMAs with k step 1's
-        // reads interleaved evenly, then k step 1's MFMAs.
-        __builtin_amdgcn_sched_group_barrier(0x100, S::READS, 0);            // DS read
-        for (int r = 0; r < S::READS; ++r) {
-            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS / S::READS, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                  // DS read
+        if constexpr (S::KSTEPS == 2) {
+            read_frags(0);
+            read_frags(1);
+            mfmas(0);
+            mfmas(1);
+            // Schedule: k step 0's fragment reads, then its MFMAs with k step
+            // 1's reads interleaved evenly, then k step 1's MFMAs.
+            __builtin_amdgcn_sched_group_barrier(0x100, S::READS, 0);            // DS read
+            for (int r = 0; r < S::READS; ++r) {
+                __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS / S::READS, 0);  // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                  // DS read
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS, 0);
+        } else {
+            read_frags(0);
+            mfmas(0);
+            // Schedule: the fragments of the first product term (hi x hi),
+            // then its MFMAs with the remaining fragment reads interleaved.
+            constexpr int first = S::RB + S::CB, rest = S::READS - first;
+            __builtin_amdgcn_sched_group_barrier(0x100, first, 0);
+            for (int r = 0; r < rest; ++r) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - rest, 0);
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS, 0);
     }
 
     // Accumulator layout of the 32x32 MFMA with the column operand first:
@@ -403,7 +469,7 @@ hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int 
 {
     const int64_t nrows = nmax - base;
     if (nrows <= 0) return hipSuccess;
-    if (kw % KC != 0) return hipErrorInvalidValue;
+    if (kw % kKAlign != 0) return hipErrorInvalidValue;
     const int64_t nc = ncols < nrows ? ncols : nrows;
     if (herm) {
         if (dtype == 0) return launch_t<double, true>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);

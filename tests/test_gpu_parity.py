@@ -244,3 +244,54 @@ def test_batched_more_workgroups_than_fit_at_once(prec):
         assert torch.equal(single["mask"], outs[i]["mask"])
         assert torch.equal(single["pivots"], outs[i]["pivots"])
         assert torch.equal(A1, As[i])
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_graph_capture_replays_equal_eager(prec):
+    """A batched call captured in a HIP graph together with the restore copies
+    and replayed several times, with eager work and host syncs in between,
+    gives the eager result bit for bit on every replay."""
+    n, count = 700, 3
+    Ks = [B.colmajor(W.hermitian_kernel(n, seed=130 + i), device=DEV) for i in range(count)]
+    us = [torch.from_numpy(W.uniform_stream(n, seed=13000 + i)).to(DEV) for i in range(count)]
+    As = [torch.empty_like(K) for K in Ks]
+    ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, [n] * count, prec),
+                     dtype=torch.uint8, device=DEV)
+    outs = [{"mask": torch.empty(n, dtype=torch.uint8, device=DEV),
+             "pivots": torch.empty(n, dtype=torch.float64, device=DEV),
+             "loglik": torch.empty(1, dtype=torch.float64, device=DEV),
+             "info": torch.empty(1, dtype=torch.int32, device=DEV)} for _ in range(count)]
+
+    def step():
+        for A, K in zip(As, Ks):
+            A.copy_(K)
+        B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, outs=outs)
+
+    step()
+    torch.cuda.synchronize()
+    eager = [(o["mask"].clone(), o["pivots"].clone(), o["loglik"].clone()) for o in outs]
+    eager_A = [A.clone() for A in As]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    for _ in range(4):
+        for o, A in zip(outs, As):
+            o["mask"].fill_(7)
+            o["pivots"].fill_(-3.0)
+            o["loglik"].fill_(0.0)
+            A.fill_(0.5)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e, eA, A in zip(outs, eager, eager_A, As):
+            assert torch.equal(o["mask"], e[0])
+            assert torch.equal(o["pivots"], e[1])
+            assert torch.equal(o["loglik"], e[2])
+            assert torch.equal(A, eA)
