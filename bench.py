@@ -51,6 +51,9 @@ def parse():
                    help="generate (and cache) K, then exit")
     p.add_argument("--no-graph", action="store_true",
                    help="launch every step eagerly instead of replaying a captured HIP graph")
+    p.add_argument("--extra", type=int, default=1,
+                   help="also measure the other workloads (n=1024 single sample, LU n=8192, "
+                        "batched L-ensembles); 0 skips them")
     return p.parse_args()
 
 
@@ -187,6 +190,194 @@ def cpu_baseline(K_host, u0, n, seconds):
             "gflops": sps * n ** 3 / 3.0 / 1e9}
 
 
+def graph_time(torch, step, reps, warmup=1):
+    """Capture step() in a HIP graph (after `warmup` eager runs) and return the
+    milliseconds per replay over `reps` replays, timed with events on the
+    replay stream."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    del g
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_plain(torch, B, W, dev, cpu):
+    """One sample of a dense Hermitian K, n = 1024 (FP64 storage), both paths:
+    latency per sample (restore + call, graph replay); with `cpu`, the oracle's
+    time for the whole sample on the host cores as its CPU baseline."""
+    n = 1024
+    Kh = W.hermitian_kernel(n, seed=1)
+    u_h = W.uniform_stream(n, seed=1000)
+    K = B.colmajor(Kh, device=dev)
+    u = torch.from_numpy(u_h).to(dev)
+    A = torch.empty_like(K)
+    out = {"workload": "K = Q diag(lam) Q^T, Q from QR of N(0,1) 1024x1024, lam ~ U(0,1); "
+                       "one sample, FP64 storage, LDL^H", "n": n}
+    for name, prec in (("split", B.DPP_PREC_SPLIT_BF16), ("fp64", B.DPP_PREC_FP64)):
+        ws = torch.empty(B.dpp_workspace_size(True, B.DPP_F64, n, prec), dtype=torch.uint8, device=dev)
+        o = {"mask": torch.empty(n, dtype=torch.uint8, device=dev),
+             "pivots": torch.empty(n, dtype=torch.float64, device=dev),
+             "loglik": torch.empty(1, dtype=torch.float64, device=dev),
+             "info": torch.empty(1, dtype=torch.int32, device=dev)}
+
+        def step():
+            A.copy_(K)
+            B.dpp_sample_ldlh(A, u, prec=prec, ws=ws, out=o)
+
+        ms = graph_time(torch, step, reps=50)
+        out[name] = {"ms_per_sample": round(ms, 4), "samples_per_s": round(1e3 / ms, 1),
+                     "tflops": round(n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 4),
+                     "size": int(o["mask"].sum().item()), "info": int(o["info"].item())}
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.ldlh(Kh, u_h)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / t, 2), "unit": "samples/s",
+                               "cores": oracle.omp_threads(), "kind": "oracle",
+                               "sample": "the whole n = 1024 sample (unblocked FP64 LDL^H)"}
+    return out
+
+
+def bench_lu(torch, B, W, dev, cpu_seconds):
+    """Non-Hermitian K = S H S^-1, n = 8192 (FP64 storage), 32 samples (four
+    batched calls of 8, each sample with its own stream), both paths, timed as
+    one graph replay of the four calls with their restores. TFLOP/s counts
+    2n^3/3 per sample. Checks: every info = 0; sample 0's mask equals the
+    LDL^H mask of H on the same stream (Prop. 2)."""
+    n, per_call, calls = 8192, 8, 4
+    K, H = W.similarity_kernel(n, seed=3, device=dev)
+    streams = [torch.from_numpy(W.uniform_stream(n, seed=3000 + i)).to(dev)
+               for i in range(per_call * calls)]
+    As = [torch.empty_like(K) for _ in range(per_call)]
+    out = {"workload": "K = S H S^-1, H = Q diag(lam) Q^T, lam ~ Beta(0.5,2), S = diag(exp z), "
+                       "z ~ N(0, 0.5); n = 8192, FP64 storage, LU; 32 samples as 4 batched calls of 8",
+           "n": n, "samples": per_call * calls}
+    for name, prec in (("split", B.DPP_PREC_SPLIT_BF16), ("fp64", B.DPP_PREC_FP64)):
+        ws = torch.empty(B.dpp_workspace_size_batched(False, B.DPP_F64, [n] * per_call, prec),
+                         dtype=torch.uint8, device=dev)
+        outs = [{"mask": torch.empty(n, dtype=torch.uint8, device=dev),
+                 "pivots": torch.empty(n, dtype=torch.float64, device=dev),
+                 "loglik": torch.empty(1, dtype=torch.float64, device=dev),
+                 "info": torch.empty(1, dtype=torch.int32, device=dev)}
+                for _ in range(per_call * calls)]
+
+        def step():
+            for c in range(calls):
+                for A in As:
+                    A.copy_(K)
+                B.dpp_sample_lu_batched(As, streams[c * per_call:(c + 1) * per_call], prec=prec,
+                                        ws=ws, outs=outs[c * per_call:(c + 1) * per_call])
+
+        ms = graph_time(torch, step, reps=2)
+        sizes = [int(o["mask"].sum().item()) for o in outs]
+        # Prop. 2: H defines the same DPP; with the same stream the masks agree
+        # up to near ties.
+        Ah = H.clone()
+        oh = B.dpp_sample_ldlh(Ah, streams[0], prec=prec)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(oh["mask"], outs[0]["mask"]))
+        del Ah, ws
+        samples = per_call * calls
+        out[name] = {"ms_per_step": round(ms, 3), "samples_per_s": round(samples / (ms * 1e-3), 3),
+                     "tflops": round(samples * 2.0 * n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3),
+                     "info_all_zero": all(int(o["info"].item()) == 0 for o in outs),
+                     "size_mean": round(float(np.mean(sizes)), 1),
+                     "mask_equals_ldlh_of_H_sample0": same}
+    if cpu_seconds > 0:
+        import oracle
+        Kh = np.asfortranarray(K.cpu().numpy())
+        u0 = streams[0].cpu().numpy()
+        del As, K, H
+        torch.cuda.empty_cache()
+        A = np.array(Kh, order="F", copy=True)
+        t0 = time.perf_counter()
+        oracle.lu(A, u0, npiv=2, inplace=True)
+        t_probe = time.perf_counter() - t0
+        p = int(max(2, min(n, cpu_seconds / max(t_probe / 2, 1e-6))))
+        A = np.array(Kh, order="F", copy=True)
+        t0 = time.perf_counter()
+        oracle.lu(A, u0, npiv=p, inplace=True)
+        t = time.perf_counter() - t0
+        j = np.arange(n, dtype=np.float64)
+        frac = float(np.sum((n - j[:p]) ** 2) / np.sum((n - j) ** 2))
+        out["cpu_baseline"] = {"value": frac / t, "unit": "samples/s", "cores": oracle.omp_threads(),
+                               "kind": "oracle",
+                               "sample": f"first {p} of {n} pivots of one sample (unblocked FP64 LU, "
+                                         f"{frac * 100:.3f}% of the 2n^3/3 work) in {t:.1f} s, scaled"}
+    return out
+
+
+def bench_lensemble(torch, B, W, dev, count=4096):
+    """`count` L-ensemble marginal kernels, n_i ~ U{64..1024}, rank 64, formed in
+    FP64 and stored FP32, one sample each in one batched LDL^H call, both paths,
+    timed as a graph replay of (restore of all working copies + the call).
+    TFLOP/s counts sum n_i^3/3. Checks: every info = 0 and |Y_i| <= 64."""
+    ns = W.lensemble_batch_sizes(count, seed=4)
+    offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
+    uoffs = np.concatenate([[0], np.cumsum(ns.astype(np.int64))])
+    Kflat = torch.empty(int(offs[-1]), dtype=torch.float32, device=dev)
+    Aflat = torch.empty_like(Kflat)
+    uflat = torch.empty(int(uoffs[-1]), dtype=torch.float64, device=dev)
+
+    def mat(flat, i):
+        n = int(ns[i])
+        return torch.as_strided(flat, (n, n), (1, n), int(offs[i]))
+
+    Ks = [mat(Kflat, i) for i in range(count)]
+    As = [mat(Aflat, i) for i in range(count)]
+    us = [uflat[int(uoffs[i]):int(uoffs[i + 1])] for i in range(count)]
+    for i in range(count):
+        W.lensemble_kernel(int(ns[i]), seed=400000 + i, out=Ks[i])
+        us[i].copy_(torch.from_numpy(W.uniform_stream(int(ns[i]), seed=4000 + i)))
+    torch.cuda.synchronize()
+    flops = float(np.sum(ns.astype(np.float64) ** 3) / 3.0)
+    out = {"workload": f"{count} L-ensemble marginal kernels K = L(L+I)^-1, L = diag(q) Phi Phi^T diag(q), "
+                       "Phi n_i x 64 ~ N(0, 1/64), q ~ LogNormal(0, 0.5), n_i ~ U{64..1024}; formed in "
+                       "FP64, stored FP32; one sample each in one batched LDL^H call",
+           "count": count, "sum_n": int(ns.sum()), "flops_per_call": flops}
+    mflat = torch.empty(int(uoffs[-1]), dtype=torch.uint8, device=dev)
+    pflat = torch.empty(int(uoffs[-1]), dtype=torch.float64, device=dev)
+    lls = torch.empty(count, dtype=torch.float64, device=dev)
+    infos = torch.empty(count, dtype=torch.int32, device=dev)
+    outs = [{"mask": mflat[int(uoffs[i]):int(uoffs[i + 1])], "pivots": pflat[int(uoffs[i]):int(uoffs[i + 1])],
+             "loglik": lls[i:i + 1], "info": infos[i:i + 1]} for i in range(count)]
+    for name, prec in (("split", B.DPP_PREC_SPLIT_BF16), ("fp64", B.DPP_PREC_FP64)):
+        ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F32, [int(x) for x in ns], prec),
+                         dtype=torch.uint8, device=dev)
+
+        def step():
+            Aflat.copy_(Kflat)
+            B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, outs=outs)
+
+        ms = graph_time(torch, step, reps=3)
+        sizes = np.array([int(x) for x in torch.stack([o["mask"].sum() for o in outs]).cpu()])
+        out[name] = {"ms_per_call": round(ms, 3), "samples_per_s": round(count / (ms * 1e-3), 1),
+                     "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                     "info_all_zero": bool((infos == 0).all().item()),
+                     "max_size": int(sizes.max()), "size_le_rank": bool((sizes <= 64).all()),
+                     "workspace_gb": round(ws.numel() / 1e9, 2)}
+        del ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -267,6 +458,19 @@ def main():
     if "fp64" in res and order[0] != "fp64":
         out["roofline_fp64"] = roofline_entry(res["fp64"]["profile"], "update_f64", PEAK_FP64)
 
+    # Share of the step in the diagonal-block chain and its panel solves, and
+    # the leaf kernel's HBM rate on its algorithmic bytes.
+    for name in order:
+        pr = res[name]["profile"]
+        tot = sum(v["ms"] for v in pr.values())
+        lf = pr.get("leaf_ldlh")
+        if lf and tot > 0:
+            out[name]["leaf"] = {"share_of_kernel_time": round(lf["ms"] / tot, 4),
+                                 "avg_launch_us": round(lf["ms"] / lf["launches"] * 1e3, 2),
+                                 "us_per_pivot": round(lf["ms"] * 1e3 / lf["launches"] / 64, 3),
+                                 "hbm_gbs_algorithmic": round(lf["bytes"] / (lf["ms"] * 1e-3) / 1e9, 1),
+                                 "hbm_frac_of_peak": round(lf["bytes"] / (lf["ms"] * 1e-3) / PEAK_HBM, 4)}
+
     if args.cpu_seconds > 0:
         log("[bench] CPU oracle baseline")
         K_host = K.cpu().numpy()
@@ -276,6 +480,17 @@ def main():
                                            args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
+    if args.extra:
+        dev = torch.device("cuda:0")
+        log("[bench] n=1024 single sample")
+        out["plain_n1024"] = bench_plain(torch, B, W, dev, args.cpu_seconds > 0)
+        torch.cuda.empty_cache()
+        log("[bench] LU n=8192")
+        out["lu_n8192"] = bench_lu(torch, B, W, dev, min(args.cpu_seconds, 10.0))
+        torch.cuda.empty_cache()
+        log("[bench] batched L-ensembles")
+        out["lensemble_batch"] = bench_lensemble(torch, B, W, dev)
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -17,13 +17,16 @@
  *     return-value strings is a DEVICE pointer owned by the caller. The library
  *     allocates no memory: all scratch space comes from the caller's workspace
  *     `ws` of `ws_bytes` bytes (query the size with dpp_workspace_size*).
- *   - Matrices are column-major with leading dimension lda >= max(1, n).
+ *   - Matrices are column-major with leading dimension max(1, n) <= lda <=
+ *     2^20 (the kernels address strips of up to 256 columns with 32-bit
+ *     byte offsets).
  *   - `stream` is a hipStream_t (NULL: the default stream). Calls are
  *     asynchronous: outputs are valid once the stream has reached the end of
  *     the call. The library issues one fixed launch sequence per call whose
  *     shape depends only on (n, dtype, precision), never on the decisions.
- *   - Argument errors (n < 1, lda < n, NULL pointers, workspace too small,
- *     unknown enum values) are returned synchronously and nothing is launched.
+ *   - Argument errors (n < 1, lda < n, lda > 2^20, NULL pointers, workspace
+ *     too small, unknown enum values) are returned synchronously and nothing
+ *     is launched.
  *   - Numerical trouble never returns an error code; it is reported in `info`
  *     (LAPACK style, see below).
  *   - Calls on one stream are ordered. Two calls that share a workspace or an

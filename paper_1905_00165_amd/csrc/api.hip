@@ -5,13 +5,13 @@
 // sampler of Sec. 2 on each 64-wide diagonal block):
 //
 //   LDL^H, outer block width B0 (FP64: 256, split-BF16: 2048):
-//     for each outer panel [j0, j1):
-//       factor_panel(j0, j1)                       -- recursive, below
+//     for each outer panel [j0, j1 = j0 + B0):
+//       factor_panel(j0, B0)                       -- recursive, below
 //       update rows/cols [j1, n) by columns [j0, j1) -- the trailing update
-//     factor_panel(c0, c1): width <= 64 -> one diagonal-block launch; else
-//       split at mid (a multiple of 64), factor_panel(c0, mid),
-//       update rows [mid, n) x cols [mid, c1) by columns [c0, mid),
-//       factor_panel(mid, c1).
+//     factor_panel(c0, w), w = 64 * 2^k: w = 64 -> one diagonal-block
+//       launch; else with mid = c0 + w/2: factor_panel(c0, w/2),
+//       update rows [mid, n) x cols [mid, mid + w/2) by columns [c0, mid),
+//       factor_panel(mid, w/2). Nodes at or past the largest n are skipped.
 //   LU: one level, B0 = 64: diagonal block + both panel solves, then the
 //     trailing update by those 64 columns.
 //   Then one finalize launch (loglik, info).
@@ -37,11 +37,11 @@ struct Plan {
     bool herm;
     int dtype;   // 0 FP64 storage, 1 FP32 storage
     bool split;  // split-BF16 updates
-    int B0;      // outer panel width (multiple of kLeaf)
-    int ss;      // row stride of the split panel copies (elements), >= B0
+    int B0;      // outer panel width (kLeaf times a power of two)
+    int ss;      // row stride of the split panel copies (elements)
 };
 
-Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec)
+Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
 {
     Plan p;
     p.herm = herm;
@@ -52,9 +52,18 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec)
     // FP64 storage; the split path needs the wider panel to stay MFMA-bound.
     if (herm) p.B0 = p.split ? 2048 : 256;
     else p.B0 = kLeaf;
-    p.ss = p.B0;
+    // The split copies hold the columns of one outer panel, at most B0 and no
+    // more than the largest problem has (rounded to whole blocks), so small
+    // batched problems keep small copies. B0 itself (the blocking) does not
+    // depend on the sizes in the batch.
+    const int64_t cap = (nmax + kLeaf - 1) / kLeaf * kLeaf;
+    p.ss = p.B0 < cap ? p.B0 : (int)cap;
     return p;
 }
+
+// Largest leading dimension: the kernels address a column strip (up to 256
+// columns of A) with 32-bit byte offsets.
+constexpr int64_t kMaxLda = (int64_t)1 << 20;
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -230,36 +239,37 @@ dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
     });
 }
 
-dpp_status factor_panel(const Ctx& c, int64_t c0, int64_t c1, int64_t j0)
+// Columns [c0, c0 + w) of the outer panel starting at j0, w = 64 * 2^k. The
+// split points form a fixed binary tree over each outer panel, whatever the
+// sizes in the batch: a problem sees the same sequence of operations (and
+// bit-identical results) alone and in any batch.
+dpp_status factor_panel(const Ctx& c, int64_t c0, int64_t w, int64_t j0)
 {
-    if (c1 - c0 <= kLeaf) return leaf(c, c0, j0);
-    const int64_t nb = (c1 - c0 + kLeaf - 1) / kLeaf;
-    const int64_t mid = c0 + ((nb + 1) / 2) * kLeaf;
-    dpp_status st = factor_panel(c, c0, mid, j0);
+    if (c0 >= c.nmax) return DPP_OK;
+    if (w <= kLeaf) return leaf(c, c0, j0);
+    const int64_t h = w / 2, mid = c0 + h;
+    dpp_status st = factor_panel(c, c0, h, j0);
+    if (st != DPP_OK || mid >= c.nmax) return st;
+    st = update(c, mid, h, c0, (int)h, j0);
     if (st != DPP_OK) return st;
-    if (mid < c.nmax) {
-        st = update(c, mid, c1 - mid, c0, (int)(mid - c0), j0);
-        if (st != DPP_OK) return st;
-    }
-    return factor_panel(c, mid, c1, j0);
+    return factor_panel(c, mid, h, j0);
 }
 
 dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
                dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
 {
     if (!probs || count < 1 || count > 65535 || !valid_enums(dt, prec)) return DPP_ERR_INVALID_ARG;
-    const Plan plan = make_plan(herm, dt, prec);
     int64_t nmax = 0;
-    size_t need = desc_bytes(count);
     for (int64_t i = 0; i < count; ++i) {
         const dpp_problem& q = probs[i];
-        if (q.n < 1 || q.lda < q.n || !q.A || !q.u || !q.mask || !q.pivots || !q.loglik ||
-            !q.info)
+        if (q.n < 1 || q.lda < q.n || q.lda > kMaxLda || !q.A || !q.u || !q.mask || !q.pivots ||
+            !q.loglik || !q.info)
             return DPP_ERR_INVALID_ARG;
-        if (q.n > (int64_t)1 << 31) return DPP_ERR_INVALID_ARG;
         nmax = q.n > nmax ? q.n : nmax;
-        need += problem_bytes(plan, q.n);
     }
+    const Plan plan = make_plan(herm, dt, prec, nmax);
+    size_t need = desc_bytes(count);
+    for (int64_t i = 0; i < count; ++i) need += problem_bytes(plan, probs[i].n);
     if (!ws || ws_bytes < need) return DPP_ERR_WORKSPACE;
     const dpp_status dev = device_ok();
     if (dev != DPP_OK) return dev;
@@ -302,8 +312,8 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     }
 
     for (int64_t j0 = 0; j0 < nmax; j0 += plan.B0) {
-        const int64_t j1 = (j0 + plan.B0 < nmax) ? j0 + plan.B0 : nmax;
-        dpp_status st = plan.herm ? factor_panel(c, j0, j1, j0) : leaf(c, j0, j0);
+        const int64_t j1 = j0 + plan.B0;
+        dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : leaf(c, j0, j0);
         if (st != DPP_OK) return st;
         if (j1 < nmax) {
             st = update(c, j1, nmax - j1, j0, (int)(j1 - j0), j0);
@@ -321,12 +331,14 @@ size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t cou
                          dpp_precision prec)
 {
     if (!ns || count < 1 || !valid_enums(dt, prec)) return 0;
-    const Plan plan = make_plan(herm, dt, prec);
-    size_t need = desc_bytes(count);
+    int64_t nmax = 0;
     for (int64_t i = 0; i < count; ++i) {
-        if (ns[i] < 1) return 0;
-        need += problem_bytes(plan, ns[i]);
+        if (ns[i] < 1 || ns[i] > kMaxLda) return 0;
+        nmax = ns[i] > nmax ? ns[i] : nmax;
     }
+    const Plan plan = make_plan(herm, dt, prec, nmax);
+    size_t need = desc_bytes(count);
+    for (int64_t i = 0; i < count; ++i) need += problem_bytes(plan, ns[i]);
     return need;
 }
 

@@ -64,36 +64,61 @@ def projection_kernel(n: int, rank: int, seed: int, device=None):
     return K.contiguous()
 
 
-def similarity_kernel(n: int, seed: int):
+def similarity_kernel(n: int, seed: int, device=None):
     """Non-Hermitian kernel of the same DPP as a Hermitian one (Prop. 2).
 
     H = Q diag(lam) Q^T with lam_i ~ Beta(0.5, 2); s_i = exp(z_i), z_i ~ N(0, 0.5)
     (standard deviation 0.5); K = S H S^{-1}, i.e. K_ij = s_i H_ij / s_j.
-    Returns (K, H).
+    Returns (K, H). With ``device`` the QR and the products run there (FP64)
+    from the same host draws, and K and H come back as column-major device
+    tensors.
     """
     rng = np.random.default_rng(seed)
-    Q = _orthonormal(rng, n, n)
+    G = rng.standard_normal((n, n))
     lam = rng.beta(0.5, 2.0, size=n)
-    H = symmetrize_lower((Q * lam) @ Q.T)
     z = rng.normal(0.0, 0.5, size=n)
     s = np.exp(z)
-    K = (s[:, None] * H) / s[None, :]
-    return np.asfortranarray(K), np.asfortranarray(H)
+    if device is None:
+        Q, _ = np.linalg.qr(G, mode="reduced")
+        H = symmetrize_lower((Q * lam) @ Q.T)
+        K = (s[:, None] * H) / s[None, :]
+        return np.asfortranarray(K), np.asfortranarray(H)
+    import torch
+    Q, _ = torch.linalg.qr(torch.from_numpy(G).to(device), mode="reduced")
+    lam_d = torch.from_numpy(lam).to(device)
+    s_d = torch.from_numpy(s).to(device)
+    H = (Q * lam_d) @ Q.T
+    del Q
+    H = torch.tril(H) + torch.tril(H, -1).T
+    K = (s_d[:, None] * H) / s_d[None, :]
+    # column-major: the transpose view of a contiguous buffer holding K^T
+    return K.T.contiguous().T, H.T.contiguous().T
 
 
-def lensemble_kernel(n: int, seed: int, rank: int = 64, dtype=np.float32) -> np.ndarray:
+def lensemble_kernel(n: int, seed: int, rank: int = 64, dtype=np.float32, out=None):
     """Marginal kernel of a rank-`rank` L-ensemble, formed in FP64, stored in `dtype`.
 
     Phi ~ N(0, 1/rank) (variance 1/rank), q_i ~ LogNormal(0, 0.5),
     F = diag(q) Phi, L = F F^T and K = L (L + I)^{-1} = F (I + F^T F)^{-1} F^T.
+    With ``out`` (a column-major n x n torch tensor on a device) the products
+    and the solve run on that device, in FP64, from the same host draws, and
+    the result is written into ``out`` in its dtype.
     """
     rng = np.random.default_rng(seed)
     Phi = rng.normal(0.0, 1.0 / np.sqrt(rank), size=(n, rank))
     q = rng.lognormal(0.0, 0.5, size=n)
     F = q[:, None] * Phi
-    M = np.eye(rank) + F.T @ F
-    K = F @ np.linalg.solve(M, F.T)
-    return np.asfortranarray(symmetrize_lower(K).astype(dtype))
+    if out is None:
+        M = np.eye(rank) + F.T @ F
+        K = F @ np.linalg.solve(M, F.T)
+        return np.asfortranarray(symmetrize_lower(K).astype(dtype))
+    import torch
+    Fd = torch.from_numpy(F).to(out.device)
+    M = torch.eye(rank, dtype=torch.float64, device=out.device) + Fd.T @ Fd
+    K = Fd @ torch.linalg.solve(M, Fd.T)
+    K = torch.tril(K) + torch.tril(K, -1).T
+    out.copy_(K)
+    return out
 
 
 def lensemble_batch_sizes(count: int, seed: int, lo: int = 64, hi: int = 1024) -> np.ndarray:

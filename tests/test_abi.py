@@ -50,6 +50,16 @@ def test_workspace_sizes():
     assert b >= (B.dpp_workspace_size(True, B.DPP_F64, 100, B.DPP_PREC_SPLIT_BF16) +
                  B.dpp_workspace_size(True, B.DPP_F64, 200, B.DPP_PREC_SPLIT_BF16) - 1024)
     assert B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 0], B.DPP_PREC_FP64) == 0
+    # The split copies are no wider than the largest problem (rounded up to
+    # 64 columns): n = 100 alone needs 4 planes of 100 x 128.
+    s100 = B.dpp_workspace_size(True, B.DPP_F64, 100, B.DPP_PREC_SPLIT_BF16)
+    f100 = B.dpp_workspace_size(True, B.DPP_F64, 100, B.DPP_PREC_FP64)
+    assert s100 - f100 == (4 * 100 * 128 * 2 + 255) // 256 * 256
+    # ... and in a batch, as wide as the batch's largest problem.
+    b2 = B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 1000], B.DPP_PREC_SPLIT_BF16)
+    f2 = B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 1000], B.DPP_PREC_FP64)
+    assert b2 - f2 == sum((4 * n * 1024 * 2 + 255) // 256 * 256 for n in (100, 1000))
+    assert B.dpp_workspace_size(True, B.DPP_F64, (1 << 20) + 1, B.DPP_PREC_FP64) == 0
 
 
 @pytest.mark.parametrize("name", ["dpp_sample_ldlh", "dpp_sample_lu"])
@@ -60,8 +70,9 @@ def test_argument_errors_return_before_any_launch(name):
     big = 1 << 40
     # n < 1
     assert f(p, 0, 0, 1, p, p, p, p, p, 0, ws, big, None) == 1
-    # lda < n
+    # lda < n, lda > 2^20
     assert f(p, 0, 10, 9, p, p, p, p, p, 0, ws, big, None) == 1
+    assert f(p, 0, 10, (1 << 20) + 1, p, p, p, p, p, 0, ws, big, None) == 1
     # null A / u / outputs
     assert f(None, 0, 10, 10, p, p, p, p, p, 0, ws, big, None) == 1
     assert f(p, 0, 10, 10, None, p, p, p, p, 0, ws, big, None) == 1

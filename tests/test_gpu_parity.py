@@ -167,10 +167,13 @@ def test_lda_padding_untouched():
     assert v.ok, v.why
 
 
+@pytest.mark.parametrize("ns", [[100, 257, 64, 1], [700, 1000, 300, 129, 1100]],
+                         ids=["small", "uneven"])
 @pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
-def test_batched_equals_single_bitwise(herm, prec):
-    ns = [100, 257, 64, 1]
+def test_batched_equals_single_bitwise(herm, prec, ns):
+    """Each problem of a batch with uneven sizes equals its single call bit for
+    bit (the blocking never depends on the other sizes in the batch)."""
     Ks = [W.hermitian_kernel(n, seed=90 + n) if herm else W.similarity_kernel(n, seed=90 + n)[0]
           for n in ns]
     us = [W.uniform_stream(n, seed=9000 + n) for n in ns]
@@ -295,3 +298,37 @@ def test_graph_capture_replays_equal_eager(prec):
             assert torch.equal(o["pivots"], e[1])
             assert torch.equal(o["loglik"], e[2])
             assert torch.equal(A, eA)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_batched_lensembles_uneven_n_fp32(prec):
+    """The batched L-ensemble workload at reduced count: 48 rank-64 kernels
+    with n_i ~ U{64..1024}, formed in FP64 and stored FP32, one batched LDL^H
+    call; every instance against the oracle on the same FP32 bytes (widened)
+    and its own stream, |Y_i| <= 64, and two instances equal to single calls."""
+    count = 48
+    ns = [int(x) for x in W.lensemble_batch_sizes(count, seed=4)]
+    Ks = [W.lensemble_kernel(n, seed=400000 + i) for i, n in enumerate(ns)]
+    us = [W.uniform_stream(n, seed=4000 + i) for i, n in enumerate(ns)]
+    As = [B.colmajor(K, device=DEV, dtype=torch.float32) for K in Ks]
+    uts = [torch.from_numpy(u).to(DEV) for u in us]
+    outs = B.dpp_sample_ldlh_batched(As, uts, prec=prec)
+    torch.cuda.synchronize()
+    tol, thr = (1e-5, 1e-6) if prec == 0 else TOL[prec]
+    worst, ties = 0.0, 0
+    for K, u, o in zip(Ks, us, outs):
+        ref = oracle.ldlh(np.asarray(K, dtype=np.float64), u)
+        v = compare(o["mask"].cpu().numpy(), o["pivots"].cpu().numpy(), float(o["loglik"].cpu()[0]),
+                    ref, u, tol, thr)
+        assert v.ok or v.near_tie, v.why
+        ties += int(v.near_tie)
+        worst = max(worst, v.max_dd)
+        assert int(o["mask"].sum().item()) <= 64
+    print(f"[accuracy] L-ensemble batch prec={PREC_ID[prec]}: max |d - d_oracle| = {worst:.3e}, "
+          f"near ties {ties}/{count}")
+    for i in (0, count - 1):
+        A1 = B.colmajor(Ks[i], device=DEV, dtype=torch.float32)
+        single = B.dpp_sample_ldlh(A1, uts[i], prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(single["mask"], outs[i]["mask"])
+        assert torch.equal(single["pivots"], outs[i]["pivots"])
