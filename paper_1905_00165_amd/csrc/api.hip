@@ -12,8 +12,11 @@
 //       launch; else with mid = c0 + w/2: factor_panel(c0, w/2),
 //       update rows [mid, n) x cols [mid, mid + w/2) by columns [c0, mid),
 //       factor_panel(mid, w/2). Nodes at or past the largest n are skipped.
-//   LU: one level, B0 = 64: diagonal block + both panel solves, then the
-//     trailing update by those 64 columns.
+//   LU, outer block width B0 = 512: for each outer panel [j0, j1), 64 columns
+//     at a time: diagonal block + both panel solves (L below, U out to n),
+//     then rank-64 updates of rows [x, n) x cols [x, j1) and rows [x, j1) x
+//     cols [j1, n), x = c0 + 64; after the panel the trailing update of
+//     [j1, n) x [j1, n) by its B0 columns.
 //   Then one finalize launch (loglik, info).
 //
 // Every grouping of the Schur updates is exact in exact arithmetic: the -1 of
@@ -50,8 +53,11 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     // Outer panel width: each trailing update reads and writes the trailing
     // matrix once, so its HBM traffic per sample is ~ 8 n^3 / (3 B0) bytes for
     // FP64 storage; the split path needs the wider panel to stay MFMA-bound.
+    // LU's rank-64 steps inside a panel touch ~ (n - j0) B0 / 2 entries of the
+    // panel and ~ (n - j1) B0 / 2 of the rows of U to its right, against
+    // (n - j1)^2 per trailing update; B0 = 512 balances them at n = 8192.
     if (herm) p.B0 = p.split ? 2048 : 256;
-    else p.B0 = kLeaf;
+    else p.B0 = 512;
     // The split copies hold the columns of one outer panel, at most B0 and no
     // more than the largest problem has (rounded to whole blocks), so small
     // batched problems keep small copies. B0 itself (the blocking) does not
@@ -179,15 +185,15 @@ dpp_status timed(const Ctx& c, int id, double flops, double bytes, F&& launch)
 
 // Algorithmic work of a Schur update of rows [base, n) x cols [base, base+ncols)
 // by kw factored columns, summed over the problems that have it.
-void update_work(const Ctx& c, int64_t base, int64_t ncols, int kw, double& flops, double& bytes)
+void update_work(const Ctx& c, const dpp::Region& rg, int kw, double& flops, double& bytes)
 {
     flops = bytes = 0.0;
     const double elt = c.plan.dtype == 0 ? 8.0 : 4.0;
     const double opnd = c.plan.split ? 4.0 : elt;  // hi+lo bf16, or one stored value
     for (int64_t n : *c.ns) {
-        const int64_t nr = n - base;
-        if (nr <= 0) continue;
-        const int64_t nc = ncols < nr ? ncols : nr;
+        const int64_t nr = (rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n) - rg.r0;
+        const int64_t nc = (rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n) - rg.c0;
+        if (nr <= 0 || nc <= 0) continue;
         const double e = c.plan.herm ? (double)nc * nr - (double)nc * (nc - 1) / 2.0
                                      : (double)nr * nc;
         flops += 2.0 * e * kw;
@@ -209,18 +215,18 @@ void leaf_work(const Ctx& c, int64_t c0, double& flops, double& bytes)
     }
 }
 
-dpp_status update(const Ctx& c, int64_t base, int64_t ncols, int64_t k0, int kw, int64_t j0)
+dpp_status update(const Ctx& c, const dpp::Region& rg, int64_t k0, int kw, int64_t j0)
 {
     double fl = 0, by = 0;
-    if (c.profiling) update_work(c, base, ncols, kw, fl, by);
+    if (c.profiling) update_work(c, rg, kw, fl, by);
     if (c.plan.split)
         return timed(c, K_UPDATE_BF16X3, fl, by, [&] {
             return dpp::launch_update_bf16x3(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax,
-                                             base, ncols, k0, kw, j0, c.plan.ss, c.s);
+                                             rg, k0, kw, j0, c.plan.ss, c.s);
         });
     return timed(c, K_UPDATE_F64, fl, by, [&] {
-        return dpp::launch_update_f64(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax, base,
-                                      ncols, k0, kw, c.s);
+        return dpp::launch_update_f64(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax, rg,
+                                      k0, kw, c.s);
     });
 }
 
@@ -250,9 +256,34 @@ dpp_status factor_panel(const Ctx& c, int64_t c0, int64_t w, int64_t j0)
     const int64_t h = w / 2, mid = c0 + h;
     dpp_status st = factor_panel(c, c0, h, j0);
     if (st != DPP_OK || mid >= c.nmax) return st;
-    st = update(c, mid, h, c0, (int)h, j0);
+    st = update(c, dpp::trailing_region(mid, h), c0, (int)h, j0);
     if (st != DPP_OK) return st;
     return factor_panel(c, mid, h, j0);
+}
+
+// LU outer panel [j0, j0 + B0): 64 columns at a time. After each diagonal
+// block (which decides its pivots and solves its rows of L below it and its
+// rows of U out to column n), two rank-64 updates bring the rest of the panel
+// and the rows of U to its right up to date: rows [x, n) x columns [x, j1)
+// and rows [x, j1) x columns [j1, n), x = c0 + 64. The trailing block
+// [j1, n) x [j1, n) waits for one update with K = B0 after the panel.
+dpp_status lu_panel(const Ctx& c, int64_t j0)
+{
+    const int64_t j1 = j0 + c.plan.B0;
+    constexpr int64_t kAll = (int64_t)1 << 62;
+    for (int64_t c0 = j0; c0 < j1 && c0 < c.nmax; c0 += kLeaf) {
+        dpp_status st = leaf(c, c0, j0);
+        if (st != DPP_OK) return st;
+        const int64_t x = c0 + kLeaf;
+        if (x >= j1 || x >= c.nmax) continue;
+        st = update(c, dpp::Region{x, kAll, x, j1 - x}, c0, kLeaf, j0);
+        if (st != DPP_OK) return st;
+        if (j1 < c.nmax) {
+            st = update(c, dpp::Region{x, j1 - x, j1, kAll}, c0, kLeaf, j0);
+            if (st != DPP_OK) return st;
+        }
+    }
+    return DPP_OK;
 }
 
 dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
@@ -313,10 +344,10 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
 
     for (int64_t j0 = 0; j0 < nmax; j0 += plan.B0) {
         const int64_t j1 = j0 + plan.B0;
-        dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : leaf(c, j0, j0);
+        dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : lu_panel(c, j0);
         if (st != DPP_OK) return st;
         if (j1 < nmax) {
-            st = update(c, j1, nmax - j1, j0, (int)(j1 - j0), j0);
+            st = update(c, dpp::trailing_region(j1, nmax - j1), j0, plan.B0, j0);
             if (st != DPP_OK) return st;
         }
     }

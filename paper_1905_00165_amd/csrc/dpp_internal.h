@@ -51,11 +51,24 @@ hipError_t launch_leaf_lu(int dtype, bool split, const DevProb* probs, int nprob
 
 // Schur-complement update of rows [base, n) x cols [base, min(base+ncols, n))
 // by the K range [k0, k0+kw) of the factored columns; herm: lower part only.
+// Region of C an update writes: rows [r0, r0 + rlen), columns [c0, c0 + clen),
+// each clipped to the problem's n. Hermitian updates take r0 == c0 and write
+// the lower part only.
+struct Region {
+    int64_t r0, rlen, c0, clen;
+};
+// Rows [base, n) x columns [base, base + ncols): the lower-trapezoid updates
+// of LDL^H and the trailing updates of LU.
+inline Region trailing_region(int64_t base, int64_t ncols)
+{
+    return Region{base, (int64_t)1 << 62, base, ncols};
+}
+
 hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
-                             int64_t base, int64_t ncols, int64_t k0, int kw, hipStream_t s);
+                             Region rg, int64_t k0, int kw, hipStream_t s);
 hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int nprob,
-                                int64_t nmax, int64_t base, int64_t ncols, int64_t k0, int kw,
-                                int64_t j0, int ss, hipStream_t s);
+                                int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
+                                hipStream_t s);
 
 // loglik (fixed-order sum of ln|piv|) and info, one workgroup per problem.
 hipError_t launch_finalize(const DevProb* probs, int nprob, hipStream_t s);

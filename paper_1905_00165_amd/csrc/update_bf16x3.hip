@@ -170,15 +170,15 @@ __device__ __forceinline__ bool grouped_tile(int64_t t, int64_t NR, int64_t NC, 
 
 template <typename T, bool HERM, class S>
 __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevProb* __restrict__ probs,
-                                                               int64_t base, int64_t ncols_req,
-                                                               int64_t k0, int kw, int64_t j0,
-                                                               int ss)
+                                                               Region rg, int64_t k0, int kw,
+                                                               int64_t j0, int ss)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
-    const int64_t nrows = n - base;
-    if (nrows <= 0 || k0 + kw > n) return;
-    const int64_t ncols = ncols_req < nrows ? ncols_req : nrows;
+    const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
+    const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
+    const int64_t nrows = rEnd - rg.r0, ncols = cEnd - rg.c0;
+    if (nrows <= 0 || ncols <= 0 || k0 + kw > n) return;
     const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (ncols + S::TN - 1) / S::TN;
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -203,9 +203,9 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     const int wave = tid >> 6;
     const int wr = wave / S::WC, wc = wave % S::WC;
 
-    const int64_t rowT0 = base + tc.i0 * S::TM;
-    const int64_t colT0 = base + tc.j0 * S::TN;
-    const int64_t colEnd = base + ncols;
+    const int64_t rowT0 = rg.r0 + tc.i0 * S::TM;
+    const int64_t colT0 = rg.c0 + tc.j0 * S::TN;
+    const int64_t colEnd = cEnd;
     const int kk0 = (int)(k0 - j0);
 
     // Direct-to-LDS copies. Copy i of a stage writes bytes [1024 i, 1024 i + 1024)
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
                 row0 = (o2 % S::W_PLANE) / S::ROWB;
             }
             const int64_t first = plane < 2 ? rowT0 : colT0;
-            const int64_t last = (plane < 2 ? n : colEnd) - 1;  // rows past it: reuse it
+            const int64_t last = (plane < 2 ? rEnd : colEnd) - 1;  // rows past it: reuse it
             int64_t g = first + row0 + rl;
             g = g < last ? g : last;
             __builtin_amdgcn_global_load_lds(
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     // Epilogue geometry (see the accumulator layout below): tile-relative row
     // i, column j; stored iff i < rlim, j < clim and (lower part) i - j >= dd.
     // Rounds r = (rb, pair of column blocks); each round is 32 values per lane.
-    const int rlim = (int)(n - rowT0);
+    const int rlim = (int)(rEnd - rowT0);
     const int clim = (int)(colEnd - colT0);
     const int dd = (int)(colT0 - rowT0);
     const int jl = wc * (S::TN / S::WC) + 4 * (lane >> 5);  // lane part of the column
@@ -430,8 +430,8 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
 }
 
 template <typename T, bool HERM, class S>
-hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, int64_t base,
-                        int64_t ncols, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, Region rg,
+                        int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
     const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (nc + S::TN - 1) / S::TN;
     const int64_t tiles = (HERM && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
@@ -444,39 +444,39 @@ hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t 
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k, dim3(grid_x, nprob), dim3(S::THREADS), S::LDS, s, probs, base, ncols,
-                       k0, kw, j0, ss);
+    hipLaunchKernelGGL(k, dim3(grid_x, nprob), dim3(S::THREADS), S::LDS, s, probs, rg, k0, kw, j0,
+                       ss);
     return hipGetLastError();
 }
 
 template <typename T, bool HERM>
-hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, int64_t base,
-                    int64_t ncols, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, Region rg,
+                    int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
     // The tile shape follows the width of the updated column range.
     if (nc <= 128)
-        return launch_shape<T, HERM, Narrow>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+        return launch_shape<T, HERM, Narrow>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
     if (nc <= 256)
-        return launch_shape<T, HERM, Medium>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
-    return launch_shape<T, HERM, Wide>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+        return launch_shape<T, HERM, Medium>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    return launch_shape<T, HERM, Wide>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
 }
 
 }  // namespace
 
 hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int nprob,
-                                int64_t nmax, int64_t base, int64_t ncols, int64_t k0, int kw,
-                                int64_t j0, int ss, hipStream_t s)
+                                int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
+                                hipStream_t s)
 {
-    const int64_t nrows = nmax - base;
-    if (nrows <= 0) return hipSuccess;
-    if (kw % kKAlign != 0) return hipErrorInvalidValue;
-    const int64_t nc = ncols < nrows ? ncols : nrows;
+    const int64_t nrows = (rg.r0 + rg.rlen < nmax ? rg.r0 + rg.rlen : nmax) - rg.r0;
+    const int64_t nc = (rg.c0 + rg.clen < nmax ? rg.c0 + rg.clen : nmax) - rg.c0;
+    if (nrows <= 0 || nc <= 0) return hipSuccess;
+    if (kw % kKAlign != 0 || (herm && rg.r0 != rg.c0)) return hipErrorInvalidValue;
     if (herm) {
-        if (dtype == 0) return launch_t<double, true>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
-        return launch_t<float, true>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+        if (dtype == 0) return launch_t<double, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        return launch_t<float, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
     }
-    if (dtype == 0) return launch_t<double, false>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
-    return launch_t<float, false>(probs, nprob, nrows, nc, base, ncols, k0, kw, j0, ss, s);
+    if (dtype == 0) return launch_t<double, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    return launch_t<float, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
 }
 
 }  // namespace dpp

@@ -6,7 +6,8 @@
 // K the symmetric form the paper notes halves the work):
 //   LDL^H: C[r][c] -= sum_k L[r][k] * d'_k * L[c][k]   (lower part only)
 //   LU:    C[r][c] -= sum_k L[r][k] * U[k][c]
-// for r in [base, n), c in [base, base+ncols). The modified pivots d'_k of
+// for r in [r0, r0 + rlen), c in [c0, c0 + clen), both clipped to n (LDL^H:
+// r0 = c0, rows to n). The modified pivots d'_k of
 // rejected indices already include the -1 of Prop. 4, so this is a plain
 // product: Prop. 5 is what makes the blocked update equal to the unblocked one.
 //
@@ -58,14 +59,15 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t NR, int64_t NC, bool 
 }
 
 template <typename T, bool HERM>
-__global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ probs, int64_t base,
-                                                  int64_t ncols_req, int64_t k0, int kw)
+__global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ probs, Region rg,
+                                                  int64_t k0, int kw)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
-    const int64_t nrows = n - base;
-    if (nrows <= 0 || k0 + kw > n) return;
-    const int64_t ncols = ncols_req < nrows ? ncols_req : nrows;
+    const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
+    const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
+    const int64_t nrows = rEnd - rg.r0, ncols = cEnd - rg.c0;
+    if (nrows <= 0 || ncols <= 0 || k0 + kw > n) return;
     const int64_t NR = (nrows + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
     // XCD-contiguous tile order (grid size is a multiple of 8).
     const int64_t per_xcd = gridDim.x / 8;
@@ -91,8 +93,8 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int64_t rowA0 = base + tc.i0;  // global row of tile row 0
-    const int64_t colB0 = base + tc.j0;  // global col of tile col 0
+    const int64_t rowA0 = rg.r0 + tc.i0;  // global row of tile row 0
+    const int64_t colB0 = rg.c0 + tc.j0;  // global col of tile col 0
 
     for (int kc = 0; kc < kw; kc += KC) {
         // A tile: rows rowA0 + i, k = k0 + kc + kk. Thread -> (i = tid % 128, kk = tid/128 + 2q).
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
             for (int q = 0; q < KC / 2; ++q) {
                 const int kk = (tid >> 7) + 2 * q;
                 const int64_t gk = k0 + kc + kk;
-                sA[kk][i] = (gr < n) ? (double)A[gr + gk * lda] : 0.0;
+                sA[kk][i] = (gr < rEnd) ? (double)A[gr + gk * lda] : 0.0;
             }
         }
         if constexpr (HERM) {
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
             for (int q = 0; q < KC / 2; ++q) {
                 const int kk = (tid >> 7) + 2 * q;
                 const int64_t gk = k0 + kc + kk;
-                sB[kk][j] = (gc < base + ncols) ? (double)A[gc + gk * lda] * piv[gk] : 0.0;
+                sB[kk][j] = (gc < cEnd) ? (double)A[gc + gk * lda] * piv[gk] : 0.0;
             }
         } else {
             // B[k][c] = U[k][c] = A[k][c]: for a column, KC consecutive k.
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
             for (int q = 0; q < TN / 16; ++q) {
                 const int j = (tid >> 4) + 16 * q;
                 const int64_t gc = colB0 + j;
-                sB[kk][j] = (gc < base + ncols) ? (double)A[gk + gc * lda] : 0.0;
+                sB[kk][j] = (gc < cEnd) ? (double)A[gk + gc * lda] : 0.0;
             }
         }
         __syncthreads();
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
-                const bool ok = gr < n && gc < base + ncols && (!HERM || gr >= gc);
+                const bool ok = gr < rEnd && gc < cEnd && (!HERM || gr >= gc);
                 cv[bj][e] = ok ? (double)rowp[gc * lda] : 0.0;
             }
 #pragma unroll
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
-                const bool ok = gr < n && gc < base + ncols && (!HERM || gr >= gc);
+                const bool ok = gr < rEnd && gc < cEnd && (!HERM || gr >= gc);
                 if (ok) rowp[gc * lda] = (T)(cv[bj][e] - acc[bi][bj][e]);
             }
     }
@@ -179,20 +181,21 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
 }  // namespace
 
 hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
-                             int64_t base, int64_t ncols, int64_t k0, int kw, hipStream_t s)
+                             Region rg, int64_t k0, int kw, hipStream_t s)
 {
-    const int64_t nrows = nmax - base;
-    if (nrows <= 0) return hipSuccess;
-    const int64_t nc = ncols < nrows ? ncols : nrows;
+    const int64_t nrows = (rg.r0 + rg.rlen < nmax ? rg.r0 + rg.rlen : nmax) - rg.r0;
+    const int64_t nc = (rg.c0 + rg.clen < nmax ? rg.c0 + rg.clen : nmax) - rg.c0;
+    if (nrows <= 0 || nc <= 0) return hipSuccess;
+    if (herm && rg.r0 != rg.c0) return hipErrorInvalidValue;
     const int64_t NR = (nrows + TM - 1) / TM, NC = (nc + TN - 1) / TN;
     const int64_t tiles = herm ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
     dim3 grid((unsigned)((tiles + 7) / 8 * 8), nprob), block(256);
     if (herm) {
-        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true>), grid, block, 0, s, probs, base, ncols, k0, kw);
-        else hipLaunchKernelGGL((update_f64<float, true>), grid, block, 0, s, probs, base, ncols, k0, kw);
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true>), grid, block, 0, s, probs, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, true>), grid, block, 0, s, probs, rg, k0, kw);
     } else {
-        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false>), grid, block, 0, s, probs, base, ncols, k0, kw);
-        else hipLaunchKernelGGL((update_f64<float, false>), grid, block, 0, s, probs, base, ncols, k0, kw);
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false>), grid, block, 0, s, probs, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, false>), grid, block, 0, s, probs, rg, k0, kw);
     }
     return hipGetLastError();
 }
