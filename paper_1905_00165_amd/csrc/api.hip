@@ -25,6 +25,7 @@
 // there is no device-to-host traffic inside a call.
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -286,6 +287,29 @@ dpp_status lu_panel(const Ctx& c, int64_t j0)
     return DPP_OK;
 }
 
+// Size groups of a batch: widths of 128 up to n = 2048, then of 1024.
+int64_t size_group(int64_t n) { return n <= 2048 ? (n + 127) / 128 : 16 + (n + 1023) / 1024; }
+
+// The launch sequence of one group of problems (descriptors c.probs[0, c.count)).
+dpp_status run_group(const Ctx& c)
+{
+    const Plan& plan = c.plan;
+    for (int64_t j0 = 0; j0 < c.nmax; j0 += plan.B0) {
+        const int64_t j1 = j0 + plan.B0;
+        dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : lu_panel(c, j0);
+        if (st != DPP_OK) return st;
+        if (j1 < c.nmax) {
+            st = update(c, dpp::trailing_region(j1, c.nmax - j1), j0, plan.B0, j0);
+            if (st != DPP_OK) return st;
+        }
+    }
+    dpp_status st = timed(c, K_STORE_DIAG, 0.0, 0.0, [&] {
+        return dpp::launch_store_diag(plan.herm, plan.dtype, c.probs, c.count, c.nmax, c.s);
+    });
+    if (st != DPP_OK) return st;
+    return timed(c, K_FINALIZE, 0.0, 0.0, [&] { return dpp::launch_finalize(c.probs, c.count, c.s); });
+}
+
 dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
                dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
 {
@@ -305,11 +329,27 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     const dpp_status dev = device_ok();
     if (dev != DPP_OK) return dev;
 
-    std::vector<DevProb> host((size_t)count);
+    // Problems sorted by size (stable) and cut into groups of similar n; each
+    // group runs its own launch sequence sized for its largest n, so small
+    // problems of a mixed batch do not ride in grids sized for the largest.
+    // The blocking never depends on the other sizes, so the grouping changes
+    // no result.
+    std::vector<int64_t> order((size_t)count);
+    for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return probs[a].n < probs[b].n; });
+
+    std::vector<DevProb> host((size_t)count);  // descriptor slot p holds problem order[p]
+    std::vector<char*> base_of((size_t)count);
     char* cursor = static_cast<char*>(ws) + desc_bytes(count);
     for (int64_t i = 0; i < count; ++i) {
+        base_of[(size_t)i] = cursor;
+        cursor += problem_bytes(plan, probs[i].n);
+    }
+    for (int64_t p = 0; p < count; ++p) {
+        const int64_t i = order[(size_t)p];
         const dpp_problem& q = probs[i];
-        DevProb& d = host[(size_t)i];
+        DevProb& d = host[(size_t)p];
         d.A = q.A;
         d.n = q.n;
         d.lda = q.lda;
@@ -318,19 +358,19 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.piv = q.pivots;
         d.loglik = q.loglik;
         d.info = q.info;
-        d.diag = reinterpret_cast<double*>(cursor);
-        d.split = plan.split ? reinterpret_cast<uint16_t*>(cursor + diag_bytes(q.n)) : nullptr;
-        cursor += problem_bytes(plan, q.n);
+        d.diag = reinterpret_cast<double*>(base_of[(size_t)i]);
+        d.split = plan.split ? reinterpret_cast<uint16_t*>(base_of[(size_t)i] + diag_bytes(q.n))
+                             : nullptr;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<int64_t> ns((size_t)count);
-    for (int64_t i = 0; i < count; ++i) ns[(size_t)i] = probs[i].n;
     bool profiling;
     {
         std::lock_guard<std::mutex> g(prof().mu);
         profiling = prof().on;
     }
-    Ctx c{plan, static_cast<const DevProb*>(ws), (int)count, nmax, s, &ns, profiling};
+    std::vector<int64_t> ns_all((size_t)count);
+    for (int64_t p = 0; p < count; ++p) ns_all[(size_t)p] = host[(size_t)p].n;
+    Ctx c{plan, static_cast<const DevProb*>(ws), (int)count, nmax, s, &ns_all, profiling};
 
     // Descriptors reach the device as kernel arguments (copied at launch), so
     // the call neither reads host memory later nor blocks the host.
@@ -342,20 +382,16 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         if (st != DPP_OK) return st;
     }
 
-    for (int64_t j0 = 0; j0 < nmax; j0 += plan.B0) {
-        const int64_t j1 = j0 + plan.B0;
-        dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : lu_panel(c, j0);
+    for (int64_t p0 = 0; p0 < count;) {
+        int64_t p1 = p0 + 1;
+        while (p1 < count && size_group(host[(size_t)p1].n) == size_group(host[(size_t)p0].n)) ++p1;
+        std::vector<int64_t> ns(ns_all.begin() + p0, ns_all.begin() + p1);
+        const Ctx g{plan, c.probs + p0, (int)(p1 - p0), host[(size_t)(p1 - 1)].n, s, &ns, profiling};
+        const dpp_status st = run_group(g);
         if (st != DPP_OK) return st;
-        if (j1 < nmax) {
-            st = update(c, dpp::trailing_region(j1, nmax - j1), j0, plan.B0, j0);
-            if (st != DPP_OK) return st;
-        }
+        p0 = p1;
     }
-    dpp_status st = timed(c, K_STORE_DIAG, 0.0, 0.0, [&] {
-        return dpp::launch_store_diag(plan.herm, plan.dtype, c.probs, c.count, nmax, s);
-    });
-    if (st != DPP_OK) return st;
-    return timed(c, K_FINALIZE, 0.0, 0.0, [&] { return dpp::launch_finalize(c.probs, c.count, s); });
+    return DPP_OK;
 }
 
 size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t count,
