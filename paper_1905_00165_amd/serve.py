@@ -1,0 +1,213 @@
+"""Continuous-batching sample server on one GPU, over the library's batched calls.
+
+Marginal kernels are registered once and stay resident in HBM. Sample requests
+(kernel id, uniform stream) arrive over time. The server keeps `slots` HIP
+streams; whenever a slot is idle it admits waiting requests, oldest first, as
+long as HBM is available under `mem_budget` for each request's working copy of
+its kernel plus its share of the workspace, and runs them as one batched call on
+that slot's stream. Batches on different slots run concurrently on the device;
+a slot's memory is released when its completion event has fired, and the next
+waiting requests are admitted as slots and memory free up.
+
+Each request's result equals a standalone call on the same kernel and stream,
+bit for bit: the library's blocking never depends on the other problems of a
+batch, and a batch touches only its own buffers.
+
+Host logic only: every sampling step runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+from . import binding as B
+
+
+@dataclass
+class Request:
+    rid: int
+    kernel: int
+    u: object            # device tensor of n uniforms (FP64)
+    arrival: float       # seconds on the server clock
+    done: float = -1.0
+    mask: object = None
+    pivots: object = None
+    loglik: float = 0.0
+    info: int = 0
+    batch: int = -1      # index of the batch that ran it
+
+
+def admit(pending, footprint, free_mem, max_batch):
+    """Admission policy: the longest prefix of `pending` (oldest first) whose
+    summed footprint fits in `free_mem`, at most `max_batch` requests. A request
+    that does not fit blocks the ones behind it (first come, first served)."""
+    take, used = [], 0
+    for r in pending:
+        if len(take) >= max_batch:
+            break
+        f = footprint(r)
+        if used + f > free_mem:
+            break
+        take.append(r)
+        used += f
+    return take, used
+
+
+@dataclass
+class _Slot:
+    stream: object
+    busy: bool = False
+    event: object = None
+    reqs: list = field(default_factory=list)
+    bufs: list = field(default_factory=list)
+    keep: object = None   # working copies and workspace, held until the event fires
+    mem: int = 0
+
+
+class Server:
+    """See the module docstring. `kernels` is a list of column-major n x n device
+    tensors (FP64 or FP32, one dtype for all); `hermitian` selects LDL^H or LU."""
+
+    def __init__(self, kernels, prec=B.DPP_PREC_SPLIT_BF16, hermitian=True, slots=4,
+                 mem_budget=16 << 30, max_batch=32):
+        import torch
+        self.torch = torch
+        self.kernels = kernels
+        self.prec = prec
+        self.hermitian = hermitian
+        self.dtype = B._dtype_code(kernels[0])
+        self.elt = kernels[0].element_size()
+        for K in kernels:
+            B._check_matrix(K)
+            if B._dtype_code(K) != self.dtype:
+                raise ValueError("all resident kernels share one dtype")
+        self.mem_budget = int(mem_budget)
+        self.max_batch = int(max_batch)
+        self.slots = [_Slot(torch.cuda.Stream(device=kernels[0].device)) for _ in range(slots)]
+        self.pending = deque()
+        self.mem_used = 0
+        self.batches = 0
+        self.max_inflight = 0
+        self.t0 = time.perf_counter()
+
+    # -- accounting ---------------------------------------------------------
+    def footprint(self, r):
+        """HBM a request holds while it runs alone: its working copy, its
+        outputs and its workspace (in a batch its split copies can be wider;
+        `batch_cost` charges that)."""
+        n = self.kernels[r.kernel].shape[0]
+        ws = B.dpp_workspace_size(self.hermitian, self.dtype, n, self.prec)
+        return n * n * self.elt + ws + n * 9 + 64
+
+    def batch_cost(self, reqs):
+        """HBM of one batched call over `reqs`: working copies, outputs and the
+        batch's workspace."""
+        if not reqs:
+            return 0
+        ns = [self.kernels[r.kernel].shape[0] for r in reqs]
+        ws = B.dpp_workspace_size_batched(self.hermitian, self.dtype, ns, self.prec)
+        return sum(n * n * self.elt + n * 9 + 64 for n in ns) + ws
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    # -- the loop -------------------------------------------------------------
+    def submit(self, r):
+        if self.footprint(r) > self.mem_budget:
+            raise ValueError(f"request {r.rid} needs more HBM than the whole budget")
+        self.pending.append(r)
+
+    def poll(self):
+        """Retire finished batches (non-blocking); returns their requests."""
+        out = []
+        for s in self.slots:
+            if s.busy and s.event.query():
+                t = self.now()
+                for r, o in zip(s.reqs, s.bufs):
+                    r.done = t
+                    r.mask, r.pivots = o["mask"], o["pivots"]
+                    r.loglik, r.info = o["loglik"], o["info"]
+                out.extend(s.reqs)
+                self.mem_used -= s.mem
+                s.busy, s.reqs, s.bufs, s.event, s.keep, s.mem = False, [], [], None, None, 0
+        return out
+
+    def dispatch(self):
+        """Admit waiting requests into every idle slot while memory allows."""
+        torch = self.torch
+        for s in self.slots:
+            if s.busy or not self.pending:
+                continue
+            free = self.mem_budget - self.mem_used
+            take, _ = admit(self.pending, self.footprint, free, self.max_batch)
+            # The batch's copies are as wide as its largest problem: charge the
+            # exact cost and give back requests from the tail until it fits.
+            used = self.batch_cost(take)
+            while take and used > free:
+                take.pop()
+                used = self.batch_cost(take)
+            if not take:
+                break
+            for _ in take:
+                self.pending.popleft()
+            dev = self.kernels[0].device
+            with torch.cuda.stream(s.stream):
+                As, us, outs = [], [], []
+                for r in take:
+                    K = self.kernels[r.kernel]
+                    A = torch.empty_like(K)
+                    A.copy_(K)
+                    n = K.shape[0]
+                    As.append(A)
+                    us.append(r.u)
+                    outs.append({"mask": torch.empty(n, dtype=torch.uint8, device=dev),
+                                 "pivots": torch.empty(n, dtype=torch.float64, device=dev),
+                                 "loglik": torch.empty(1, dtype=torch.float64, device=dev),
+                                 "info": torch.empty(1, dtype=torch.int32, device=dev)})
+                ns = [A.shape[0] for A in As]
+                ws = torch.empty(max(B.dpp_workspace_size_batched(self.hermitian, self.dtype, ns,
+                                                                  self.prec), 1),
+                                 dtype=torch.uint8, device=dev)
+                f = B.dpp_sample_ldlh_batched if self.hermitian else B.dpp_sample_lu_batched
+                f(As, us, prec=self.prec, ws=ws, outs=outs)
+                ev = torch.cuda.Event()
+                ev.record(s.stream)
+            for r in take:
+                r.batch = self.batches
+            self.batches += 1
+            s.busy, s.event, s.reqs, s.bufs, s.mem = True, ev, take, outs, used
+            s.keep = (As, ws)
+            self.mem_used += used
+        self.max_inflight = max(self.max_inflight, sum(s.busy for s in self.slots))
+
+    def run(self, requests):
+        """Serve `requests` (sorted by arrival time, seconds from now) to the end:
+        each is submitted once the clock passes its arrival. Their streams `u`
+        must already be on the device and ready (synchronize after making them).
+        Returns the requests with completion times and results filled in."""
+        self.t0 = time.perf_counter()
+        todo = deque(requests)
+        finished = 0
+        while finished < len(requests):
+            t = self.now()
+            while todo and todo[0].arrival <= t:
+                self.submit(todo.popleft())
+            finished += len(self.poll())
+            self.dispatch()
+            if not any(s.busy for s in self.slots) and not self.pending and todo:
+                # idle until the next arrival
+                wait = todo[0].arrival - self.now()
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+        return requests
+
+
+def latency_stats(requests):
+    """p50 / p99 / mean latency (seconds) and the served rate."""
+    import numpy as np
+    lat = np.array([r.done - r.arrival for r in requests])
+    span = max(r.done for r in requests) - min(r.arrival for r in requests)
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "samples_per_s": len(requests) / span,
+            "requests": len(requests)}
