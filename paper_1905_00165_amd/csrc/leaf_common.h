@@ -11,8 +11,9 @@
 //      with one row of the block per lane, held in registers; the column that
 //      drives each rank-one update is broadcast through LDS.
 //   2. solves its share of the panel below the block against the factored
-//      block (and, for LU, of the row panel to its right), one row (column)
-//      per thread with the factored block in LDS.
+//      block (and, for LU, of the row panel to its right) on the matrix
+//      cores, in groups of 16 rows (columns), with the factored block and the
+//      inverses of its 16x16 diagonal blocks in LDS (solve_group below).
 // Every workgroup of a launch makes the same decisions from the same data
 // (the chain is deterministic), so the panel solves need no second launch;
 // workgroup 0 alone writes the block, the mask and the pivots.
@@ -24,7 +25,13 @@ namespace dpp {
 namespace leaf {
 
 constexpr int L = kLeaf;
-constexpr int kRowsPerWG = 512;  // one panel row per thread; 8 wavefronts
+// Panel solves: 4 wavefronts per workgroup, each 4 groups of 16 panel rows
+// (or columns), so 256 per workgroup; a staged 16 x 64 tile per wavefront.
+constexpr int kWaves = 4;
+constexpr int kGroups = 4;
+constexpr int kRows = kWaves * kGroups * 16;
+constexpr int kThreads = kWaves * 64;
+constexpr int kTilePitch = 66;  // doubles per row of a staged 16 x 64 tile
 
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
@@ -92,6 +99,64 @@ __device__ __forceinline__ void split_bf16(double x, uint16_t& hi, uint16_t& lo)
     const uint32_t xh = bf16_bits((float)x);
     hi = (uint16_t)xh;
     lo = (uint16_t)bf16_bits((float)(x - (double)bf16_value(xh)));
+}
+
+// ------------------------------------------------------------ panel solves
+// Rows of a panel solved against the factored 64x64 diagonal block on the
+// matrix cores. A solve of the form X T^T = A (T lower triangular, 64 x 64)
+// is cut into four 16-column blocks,
+//   X_b^T = T_bb^{-1} (A_b^T - sum_{c<b} T_bc X_c^T),   b = 0..3,
+// one v_mfma_f64_16x16x4f64 per 4-deep slab. The product leaves element e of
+// lane l at row l/16 + 4e, column l%16 of the 16x16 result and takes its
+// right-hand operand for slab s from row l/16, column l%16 of that slab, so
+// element s of one product is, lane for lane, slab s of the right-hand operand
+// of the next: a group of 16 rows never leaves registers.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One group of 16 rows. Lane (q, i16) = (lane / 16, lane % 16) holds in
+// cur[4b + e] row i16, column 16b + 4e + q of A and receives the same entry
+// of X in x[b][e]. Tt[t * 64 + k] = T[k][t] (T's columns, or equivalently the
+// rows of T^T); Inv[b * 256 + i * 16 + k] = (T_bb^{-1})[i][k].
+__device__ __forceinline__ void solve_group(const double* Tt, const double* Inv,
+                                            const double (&cur)[16], d4 (&x)[4], int q, int i16)
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        d4 acc = {cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3]};
+#pragma unroll
+        for (int c = 0; c < b; ++c)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc = mfma16(-Tt[(16 * c + 4 * s + q) * L + 16 * b + i16], x[c][s], acc);
+        d4 xb = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) xb = mfma16(Inv[b * 256 + i16 * 16 + 4 * s + q], acc[s], xb);
+        x[b] = xb;
+    }
+}
+
+// Inverses of the four 16x16 diagonal blocks of T (lower triangular; unit
+// diagonal if UNIT, else the diagonal Tt[(16b+k) * 65]) by forward
+// substitution, one column per lane of the calling wavefront.
+template <bool UNIT>
+__device__ __forceinline__ void invert_diag_blocks(const double* Tt, double* Inv, int lane)
+{
+    const int b = lane >> 4, c = lane & 15;
+    double y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        double acc = (k == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < k; ++t) acc -= Tt[(16 * b + t) * L + 16 * b + k] * y[t];
+        y[k] = UNIT ? acc : acc / Tt[(16 * b + k) * (L + 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Inv[b * 256 + k * 16 + c] = y[k];
 }
 
 // Write the hi/lo BF16 split of v[0..63] to two rows (64 bf16 each, 16-byte

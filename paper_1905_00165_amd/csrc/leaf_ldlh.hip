@@ -7,18 +7,6 @@ namespace {
 
 using namespace leaf;
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int kWaves = 4;                   // wavefronts per workgroup
-constexpr int kGroups = 4;                  // 16-row groups per wavefront
-constexpr int kRows = kWaves * kGroups * 16;  // panel rows per workgroup
-constexpr int kThreads = kWaves * 64;
-constexpr int kTilePitch = 66;              // doubles per row of a staged 16 x 64 tile
-
-__device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // ------------------------------------------------------------------- LDL^H
 // Step 1 (wavefront 0, every workgroup): the unblocked sampler on the 64x64
@@ -132,31 +120,13 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
     // ragged block is the last one), so bs == L from here on.
     if (row0 >= n) return;
 
-    if (tid < 64) {
-        // Column c of L_bb^{-1}: solve L_bb y = e_c by forward substitution.
-        const int b = tid >> 4, c = tid & 15;
-        double y[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            double acc = (k == c) ? 1.0 : 0.0;
-#pragma unroll
-            for (int t = 0; t < k; ++t) acc -= sL[(16 * b + t) * L + 16 * b + k] * y[t];
-            y[k] = acc;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) sI[b * 256 + k * 16 + c] = y[k];
-    }
+    if (tid < 64) invert_diag_blocks<true>(sL, sI, tid);  // L_bb^{-1}
     __syncthreads();
 
     const int lane = tid & 63;
     const int q = lane >> 4, i16 = lane & 15;
     const int64_t wrow0 = row0 + (int64_t)(tid >> 6) * (kGroups * 16);
     if (wrow0 >= n) return;
-
-    // Left-hand operands, slab s: lane holds [row i16][column 4s + q] of
-    // -L_bc (c < b) or of L_bb^{-1}; read from LDS for every row group.
-    auto frag_o = [&](int b, int c, int s) { return -sL[(16 * c + 4 * s + q) * L + 16 * b + i16]; };
-    auto frag_i = [&](int b, int s) { return sI[b * 256 + i16 * 16 + 4 * s + q]; };
 
     // Strip = columns [c0, c0+64) from row wrow0 on; lane (q, i16) of group g
     // reads row wrow0 + 16g + i16 of columns q + 4e + 16b.
@@ -186,18 +156,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
             for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
         }
         d4 x[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            d4 acc = {cur[4 * b], cur[4 * b + 1], cur[4 * b + 2], cur[4 * b + 3]};
-#pragma unroll
-            for (int c = 0; c < b; ++c)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc = mfma16(frag_o(b, c, s), x[c][s], acc);
-            d4 xb = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s = 0; s < 4; ++s) xb = mfma16(frag_i(b, s), acc[s], xb);
-            x[b] = xb;
-        }
+        solve_group(sL, sI, cur, x, q, i16);  // W = A21 L11^{-T}
         // x[b][e] = W[row][16b + 4e + q], row = wrow0 + 16g + i16.
         const int64_t r = wrow0 + 16 * g + i16;
         if constexpr (SPLIT) {

@@ -7,62 +7,99 @@ namespace {
 using namespace leaf;
 
 // ---------------------------------------------------------------------- LU
+// Step 1 (wavefront 0, every workgroup): the unblocked sampler on the 64x64
+// diagonal block, one block row per lane; at pivot j the row of U is
+// broadcast through LDS and the rows below take the rank-one update.
+//
+// Step 2: both panels, with the factored block L11 (unit lower) and U11
+// (upper, the modified pivots on its diagonal), each as solves X T^T = A of
+// leaf_common.h's solve_group:
+//   column panel, rows r below the block: L21 U11 = A21, i.e. X = A21 with
+//     T = U11^T (lower, non-unit);
+//   row panel, columns r right of the block: L11 U12 = A12, i.e. for each
+//     column U12^T L11^T = A12^T: X = A12^T with T = L11 (unit lower).
+// The row panel's columns are contiguous in memory; they pass through the
+// wavefront's LDS tile so that loads and stores stay coalesced. A receives L21
+// and U12; the split planes, hi/lo of L21 by row and of U12^T by column.
+// Each workgroup takes 256 rows of the column panel and 256 columns of the
+// row panel (splitting them over separate workgroups measured slower: the
+// chain, repeated per workgroup, dominates).
 template <typename T, bool SPLIT>
-__global__ __launch_bounds__(kRowsPerWG) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
-                                               int64_t j0, int ss)
+__global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
+                                             int64_t j0, int ss)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
     if (c0 >= n) return;
     const int bs = (int)((n - c0) < L ? (n - c0) : L);
-    const int64_t idx0 = c0 + bs + (int64_t)blockIdx.x * kRowsPerWG;
+    const int64_t idx0 = c0 + bs + (int64_t)blockIdx.x * kRows;
     if (blockIdx.x > 0 && idx0 >= n) return;
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
 
-    __shared__ double sL[L * L];  // sL[t*L + k] = L11[k][t]  (strict lower, column t)
-    __shared__ double sU[L * L];  // sU[t*L + k] = U11[t][k]  (upper with diagonal, row t)
-    __shared__ double sB[L];      // broadcast row of the current pivot
+    // sT (the tiles) comes first; the chain's broadcast row sB borrows it.
+    // The triangles as Tt[t*L + k] = T[k][t] for solve_group: the row panel
+    // uses T = L11 (sL[t*L + k] = L11[k][t], k > t), the column panel
+    // T = U11^T (sU[t*L + k] = U11[t][k], k >= t); zero elsewhere.
+    __shared__ double smem[kWaves * 16 * kTilePitch + 2 * L * L + 2 * 4 * 16 * 16];
+    double* const sT = smem;
+    double* const sB = smem;                         // chain only
+    double* const sL = smem + kWaves * 16 * kTilePitch;
+    double* const sU = sL + L * L;
+    double* const sIL = sU + L * L;                  // inverses of the diagonal blocks of L11
+    double* const sIU = sIL + 4 * 16 * 16;           // ... and of U11^T
 
     const int tid = threadIdx.x;
     if (tid < L) {
         const int lane = tid;
         double a[L];  // row `lane` of the block
+        {
+            // Buffer loads: the column offset is a scalar, so the 64 loads
+            // share one address register; reads past the end of A return 0.
+            const int64_t base = c0 + c0 * lda;
+            const __amdgpu_buffer_rsrc_t rb =
+                strip_rsrc(A + base, ((n - 1) * lda + n - base) * (int64_t)sizeof(T));
+            const int cs = (int)(lda * (int64_t)sizeof(T));
 #pragma unroll
-        for (int k = 0; k < L; ++k)
-            a[k] = (lane < bs && k < bs) ? (double)A[(c0 + lane) + (c0 + k) * lda] : 0.0;
+            for (int k = 0; k < L; ++k) {
+                const double v = buf_load<T>(rb, lane * (int)sizeof(T), k * cs);
+                a[k] = (lane < bs && k < bs) ? v : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < L; ++k) asm volatile("" : "+v"(a[k]));
+        }
         const double ul = lane < bs ? P.u[c0 + lane] : 2.0;
         double mydp = 1.0;
         int mykeep = 0;
+        int me = lane;
 
 #pragma unroll
         for (int j = 0; j < L; ++j) {
+            // Keeps the per-step lane masks from being hoisted out of the
+            // unrolled loop into scalar registers (and spilled).
+            asm volatile("" : "+v"(me));
             if (j < bs) {
                 const double d = readlane_d(a[j], j);
                 const double uj = readlane_d(ul, j);
-                const bool keep = uj < d;
-                const double dp = keep ? d : d - 1.0;
-                if (lane == j) {
+                const bool keep = uj < d;                // Bernoulli(d) with stream u_j
+                const double dp = keep ? d : d - 1.0;   // Prop. 4 on rejection
+                const bool isj = me == j, below = me > j;
+                if (isj) {
 #pragma unroll
                     for (int k = 0; k < L; ++k)
                         if (k > j) sB[k] = a[k];  // row j of U
                 }
                 __builtin_amdgcn_wave_barrier();
-                // Only rows below the pivot are updated: rows <= j already hold
-                // final entries of U.
-                const double l = (lane > j) ? a[j] / dp : 0.0;
+                // Rows at or above the pivot keep their entries (rows of U).
+                const double l = below ? a[j] / dp : 0.0;
 #pragma unroll
                 for (int k = 0; k < L; ++k)
                     if (k > j) a[k] -= l * sB[k];
                 __builtin_amdgcn_wave_barrier();
-                if (lane == j) {
-                    a[j] = dp;
-                    mydp = dp;
-                    mykeep = keep ? 1 : 0;
-                } else if (lane > j) {
-                    a[j] = l;
-                }
+                a[j] = isj ? dp : (below ? l : a[j]);
+                mydp = isj ? dp : mydp;
+                mykeep = isj ? (keep ? 1 : 0) : mykeep;
             }
         }
 
@@ -85,57 +122,127 @@ __global__ __launch_bounds__(kRowsPerWG) void leaf_lu(const DevProb* __restrict_
         }
     }
     __syncthreads();
-
     // Rows below and columns right of a block exist only when the block is a
-    // full 64 wide (a ragged block is the last one), so bs == L here.
-    const int64_t r = idx0 + tid;
-    if (r < n) {
-        const int voff = tid * (int)sizeof(T);
-        const int cstride = (int)(lda * (int64_t)sizeof(T));
-        // Column panel: L21 = A21 U11^{-1}, row r: x U11 = a.
-        {
-            const __amdgpu_buffer_rsrc_t rs =
-                strip_rsrc(A + idx0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
-            double x[L];
+    // full 64 wide (a ragged block is the last one), so bs == L from here on.
+    if (idx0 >= n) return;
+
+    // U11^T is lower triangular with the pivots on its diagonal; L11 has a
+    // unit diagonal.
+    if (tid < 64) invert_diag_blocks<true>(sL, sIL, tid);
+    else if (tid < 128) invert_diag_blocks<false>(sU, sIU, tid - 64);
+    __syncthreads();
+
+    const int lane = tid & 63;
+    const int q = lane >> 4, i16 = lane & 15;
+    const int64_t w0 = idx0 + (int64_t)(tid >> 6) * (kGroups * 16);
+    if (w0 >= n) return;
+    const int ngroups = (int)((n - w0 + 15) / 16) < kGroups ? (int)((n - w0 + 15) / 16) : kGroups;
+    double* const tile = sT + (tid >> 6) * (16 * kTilePitch);
+    const int cstride = (int)(lda * (int64_t)sizeof(T));
+
+    // Split planes from the tile: lane l writes row l/4 (of the group),
+    // entries 8(l%4) + [0, 8) and 32 + 8(l%4) + [0, 8), 16-byte pieces.
+    auto planes_from_tile = [&](int64_t gr0, int plane_hi) {
+        const int tr = lane >> 2, tc = 8 * (lane & 3);
+        const int64_t rr = gr0 + tr;
+        if (rr >= n) return;
+        const int64_t off = rr * ss + (int)(c0 - j0) + tc;
 #pragma unroll
-            for (int k = 0; k < L; ++k) x[k] = buf_load<T>(rs, voff, k * cstride);
+        for (int half = 0; half < 2; ++half) {
+            uint32_t h[4], lo[4];
 #pragma unroll
-            for (int t = 0; t < L; ++t) {
-                x[t] = x[t] / sU[t * L + t];
-                const double xt = x[t];
-#pragma unroll
-                for (int k = 0; k < L; ++k)
-                    if (k > t) x[k] -= xt * sU[t * L + k];
+            for (int p2 = 0; p2 < 4; ++p2) {
+                uint16_t h0, l0, h1, l1;
+                const int col = 32 * half + tc + 2 * p2;
+                split_bf16(tile[tr * kTilePitch + col], h0, l0);
+                split_bf16(tile[tr * kTilePitch + col + 1], h1, l1);
+                h[p2] = h0 | ((uint32_t)h1 << 16);
+                lo[p2] = l0 | ((uint32_t)l1 << 16);
             }
+            const int64_t o = off + 32 * half;
+            *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, plane_hi) + o) =
+                make_uint4(h[0], h[1], h[2], h[3]);
+            *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, plane_hi + 1) + o) =
+                make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        }
+    };
+
+    // ---- column panel: rows w0 + 16g + i16 of columns [c0, c0+64) ----------
+    {
+        const __amdgpu_buffer_rsrc_t rs =
+            strip_rsrc(A + w0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
+        auto voff_of = [&](int g) {
+            const int64_t r = w0 + 16 * g + i16;
+            const int rr = (int)((r < n ? r : n - 1) - w0);  // tail rows re-read the last row
+            return rr * (int)sizeof(T) + q * cstride;
+        };
+        double nxt[16];
+        {
+            const int v = voff_of(0);
 #pragma unroll
-            for (int k = 0; k < L; ++k) buf_store<T>(x[k], rs, voff, k * cstride);
+            for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+        }
+        for (int g = 0; g < ngroups; ++g) {
+            double cur[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+            if (g + 1 < ngroups) {
+                const int v = voff_of(g + 1);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+            }
+            d4 x[4];
+            solve_group(sU, sIU, cur, x, q, i16);  // L21 = A21 U11^{-1}
+            if (w0 + 16 * g + i16 < n) {
+                const int v = voff_of(g);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) buf_store<T>(x[b][e], rs, v, (16 * b + 4 * e) * cstride);
+            }
             if constexpr (SPLIT) {
-                const int64_t off = r * ss + (int)(c0 - j0);
-                store_split_row(split_plane(P.split, n, ss, 0) + off,
-                                split_plane(P.split, n, ss, 1) + off, x, L);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) tile[i16 * kTilePitch + 16 * b + 4 * e + q] = x[b][e];
+                __builtin_amdgcn_wave_barrier();
+                planes_from_tile(w0 + 16 * g, 0);
+                __builtin_amdgcn_wave_barrier();
             }
         }
-        // Row panel: U12 = L11^{-1} A12, column r: L11 y = a (64 contiguous
-        // entries of column r).
-        {
-            T* col = A + c0 + r * lda;
-            double y[L];
+    }
+
+    // ---- row panel: columns w0 + 16g + i of rows [c0, c0+64) ---------------
+    // Lane l moves column l/4, entries 16(l%4) + [0, 16), through the tile.
+    {
+        const int tcl = lane >> 2, tk = 16 * (lane & 3);
+        for (int g = 0; g < ngroups; ++g) {
+            const int64_t col = w0 + 16 * g + tcl;
+            const T* src = A + c0 + col * lda + tk;
 #pragma unroll
-            for (int k = 0; k < L; ++k) y[k] = (double)col[k];
+            for (int k = 0; k < 16; ++k)
+                tile[tcl * kTilePitch + tk + k] = col < n ? (double)src[k] : 0.0;
+            __builtin_amdgcn_wave_barrier();
+            double cur[16];
 #pragma unroll
-            for (int t = 0; t < L; ++t) {
-                const double yt = y[t];
+            for (int b = 0; b < 4; ++b)
 #pragma unroll
-                for (int k = 0; k < L; ++k)
-                    if (k > t) y[k] -= yt * sL[t * L + k];
+                for (int e = 0; e < 4; ++e) cur[4 * b + e] = tile[i16 * kTilePitch + 16 * b + 4 * e + q];
+            __builtin_amdgcn_wave_barrier();
+            d4 x[4];
+            solve_group(sL, sIL, cur, x, q, i16);  // U12^T = A12^T L11^{-T}
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) tile[i16 * kTilePitch + 16 * b + 4 * e + q] = x[b][e];
+            __builtin_amdgcn_wave_barrier();
+            if (col < n) {
+                T* dst = A + c0 + col * lda + tk;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) dst[k] = (T)tile[tcl * kTilePitch + tk + k];
             }
-#pragma unroll
-            for (int k = 0; k < L; ++k) col[k] = (T)y[k];
-            if constexpr (SPLIT) {
-                const int64_t off = r * ss + (int)(c0 - j0);
-                store_split_row(split_plane(P.split, n, ss, 2) + off,
-                                split_plane(P.split, n, ss, 3) + off, y, L);
-            }
+            if constexpr (SPLIT) planes_from_tile(w0 + 16 * g, 2);
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
@@ -145,8 +252,8 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
                     int64_t j0, int ss, hipStream_t s)
 {
     const int64_t below = nmax - c0 - L;
-    const int gx = below > 0 ? (int)((below + kRowsPerWG - 1) / kRowsPerWG) : 1;
-    dim3 grid(gx, nprob), block(kRowsPerWG);
+    const int gx = below > 0 ? (int)((below + kRows - 1) / kRows) : 1;
+    dim3 grid(gx, nprob), block(kThreads);
     if (split) hipLaunchKernelGGL((leaf_lu<T, true>), grid, block, 0, s, probs, c0, j0, ss);
     else hipLaunchKernelGGL((leaf_lu<T, false>), grid, block, 0, s, probs, c0, j0, ss);
     return hipGetLastError();
@@ -155,7 +262,7 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
 }  // namespace
 
 hipError_t launch_leaf_lu(int dtype, bool split, const DevProb* probs, int nprob, int64_t nmax,
-                      int64_t c0, int64_t j0, int ss, hipStream_t s)
+                          int64_t c0, int64_t j0, int ss, hipStream_t s)
 {
     if (dtype == 0) return launch_t<double>(split, probs, nprob, nmax, c0, j0, ss, s);
     return launch_t<float>(split, probs, nprob, nmax, c0, j0, ss, s);
