@@ -57,7 +57,7 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     // LU's rank-64 steps inside a panel touch ~ (n - j0) B0 / 2 entries of the
     // panel and ~ (n - j1) B0 / 2 of the rows of U to its right, against
     // (n - j1)^2 per trailing update; B0 = 512 balances them at n = 8192.
-    if (herm) p.B0 = p.split ? 2048 : 256;
+    if (herm) p.B0 = p.split ? 4096 : 256;
     else p.B0 = 512;
     // The split copies hold the columns of one outer panel, at most B0 and no
     // more than the largest problem has (rounded to whole blocks), so small
@@ -77,7 +77,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 size_t split_bytes(const Plan& p, int64_t n)
 {
-    return p.split ? align_up((size_t)4 * (size_t)n * (size_t)p.ss * sizeof(uint16_t)) : 0;
+    return p.split ? align_up((size_t)4 * (size_t)dpp::plane_rows(n) * (size_t)p.ss * sizeof(uint16_t))
+                   : 0;
 }
 size_t diag_bytes(int64_t n)
 {

@@ -26,14 +26,25 @@ struct DevProb {
                       // block b at diag[b * 64 * 64]; copied into A at the end
 };
 
-// Split-BF16 panel copies of problem p live at split[q * n * ss + r * ss + kk],
-// q = 0: hi(L), 1: lo(L), 2: hi(B), 3: lo(B), r the global row of L (or the
-// global column of the update for B), kk = k - j0 the column of the current
-// outer panel. For LDL^H, B = L D (the scaled column, W); for LU, B = U^T.
-// Values are bf16 bit patterns.
+// Split-BF16 panel copies of a problem: four planes q = 0: hi(L), 1: lo(L),
+// 2: hi(B), 3: lo(B), entry (r, kk) with r the global row of L (or the global
+// column of the update for B) and kk = k - j0 the column within the current
+// outer panel (ss columns per row, a multiple of 64). For LDL^H, B = L D (the
+// scaled column, W); for LU, B = U^T. Values are bf16 bit patterns.
+// Each plane is tiled in blocks of 32 rows x 32 columns (2 KiB), row blocks
+// outer, and inside a block by halves of 16 columns: a half holds its 32 rows
+// of 16 values (32 bytes) back to back. So the 16 rows x 32 columns an update
+// stage copies are two contiguous 512-byte runs, and 32 rows x 16 columns one
+// 1 KiB run; 8 consecutive columns of one row (16 bytes) stay contiguous.
+__host__ __device__ inline int64_t plane_rows(int64_t n) { return (n + 31) / 32 * 32; }
 __host__ __device__ inline uint16_t* split_plane(uint16_t* base, int64_t n, int ss, int q)
 {
-    return base + (int64_t)q * n * ss;
+    return base + (int64_t)q * plane_rows(n) * ss;
+}
+__host__ __device__ inline int64_t plane_off(int64_t r, int kk, int ss)
+{
+    return ((r >> 5) * (ss >> 5) + (kk >> 5)) * 1024 + ((kk >> 4) & 1) * 512 + (r & 31) * 16 +
+           (kk & 15);
 }
 
 // ------------------------------------------------------------------ launchers

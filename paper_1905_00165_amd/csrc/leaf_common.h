@@ -159,33 +159,5 @@ __device__ __forceinline__ void invert_diag_blocks(const double* Tt, double* Inv
     for (int k = 0; k < 16; ++k) Inv[b * 256 + k * 16 + c] = y[k];
 }
 
-// Write the hi/lo BF16 split of v[0..63] to two rows (64 bf16 each, 16-byte
-// aligned), as 8 stores of 16 bytes per row.
-__device__ __forceinline__ void store_split_row(uint16_t* hi_row, uint16_t* lo_row,
-                                                const double (&v)[L], int bs)
-{
-#pragma unroll
-    for (int g = 0; g < L / 8; ++g) {
-        uint32_t h[4], l[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            uint32_t hh[2], ll[2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int k = g * 8 + e * 2 + t;
-                const double x = (k < bs) ? v[k] : 0.0;
-                const uint32_t xh = bf16_bits((float)x);
-                const double rem = x - (double)bf16_value(xh);
-                hh[t] = xh;
-                ll[t] = bf16_bits((float)rem);
-            }
-            h[e] = hh[0] | (hh[1] << 16);
-            l[e] = ll[0] | (ll[1] << 16);
-        }
-        *reinterpret_cast<uint4*>(hi_row + g * 8) = make_uint4(h[0], h[1], h[2], h[3]);
-        *reinterpret_cast<uint4*>(lo_row + g * 8) = make_uint4(l[0], l[1], l[2], l[3]);
-    }
-}
-
 }  // namespace leaf
 }  // namespace dpp

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
             const int tr = lane >> 2, tc = 8 * (lane & 3);
             const int64_t rr = wrow0 + 16 * g + tr;
             if (rr < n) {
-                const int64_t off = rr * ss + (int)(c0 - j0) + tc;
+                const int kk = (int)(c0 - j0) + tc;
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     uint32_t wh[4], wl[4], lh[4], ll[4];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
                         lh[p2] = a0 | ((uint32_t)a1 << 16);
                         ll[p2] = b0 | ((uint32_t)b1 << 16);
                     }
-                    const int64_t o = off + 32 * half;
+                    const int64_t o = plane_off(rr, kk + 32 * half, ss);
                     *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 2) + o) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
                     *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 3) + o) = make_uint4(wl[0], wl[1], wl[2], wl[3]);
                     *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 0) + o) = make_uint4(lh[0], lh[1], lh[2], lh[3]);

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
         const int tr = lane >> 2, tc = 8 * (lane & 3);
         const int64_t rr = gr0 + tr;
         if (rr >= n) return;
-        const int64_t off = rr * ss + (int)(c0 - j0) + tc;
+        const int kk = (int)(c0 - j0) + tc;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             uint32_t h[4], lo[4];
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
                 h[p2] = h0 | ((uint32_t)h1 << 16);
                 lo[p2] = l0 | ((uint32_t)l1 << 16);
             }
-            const int64_t o = off + 32 * half;
+            const int64_t o = plane_off(rr, kk + 32 * half, ss);
             *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, plane_hi) + o) =
                 make_uint4(h[0], h[1], h[2], h[3]);
             *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, plane_hi + 1) + o) =

@@ -8,8 +8,9 @@
 // stored value in FP64 and rounded to the storage type.
 //
 // Operands come from the split copies the diagonal-block kernel writes while it
-// solves the panel, row-major [row][k] (k contiguous), so 16 bytes are the 8
-// consecutive k one MFMA lane holds:
+// solves the panel, tiled so that the rows one stage copies are contiguous
+// (plane_off in dpp_internal.h); 16 bytes are the 8 consecutive k one MFMA
+// lane holds:
 //   rows of C: hi/lo of L;  cols of C: hi/lo of W = L D (LDL^H) or of U^T (LU).
 //
 // Tiling (template Shape): a workgroup owns a TM x TN tile of C split over
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
             int64_t g = first + row0 + rl;
             g = g < last ? g : last;
             __builtin_amdgcn_global_load_lds(
-                (gptr_t)(split_plane(P.split, n, ss, plane) + g * ss + kk0 + kc + seg8),
+                (gptr_t)(split_plane(P.split, n, ss, plane) + plane_off(g, kk0 + kc + seg8, ss)),
                 (lptr_t)(lds + buf * S::BUF + off), 16, 0, 0);
         }
     };

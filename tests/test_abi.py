@@ -51,14 +51,15 @@ def test_workspace_sizes():
                  B.dpp_workspace_size(True, B.DPP_F64, 200, B.DPP_PREC_SPLIT_BF16) - 1024)
     assert B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 0], B.DPP_PREC_FP64) == 0
     # The split copies are no wider than the largest problem (rounded up to
-    # 64 columns): n = 100 alone needs 4 planes of 100 x 128.
+    # 64 columns), with rows padded to blocks of 32: n = 100 alone needs 4
+    # planes of 128 x 128.
     s100 = B.dpp_workspace_size(True, B.DPP_F64, 100, B.DPP_PREC_SPLIT_BF16)
     f100 = B.dpp_workspace_size(True, B.DPP_F64, 100, B.DPP_PREC_FP64)
-    assert s100 - f100 == (4 * 100 * 128 * 2 + 255) // 256 * 256
+    assert s100 - f100 == (4 * 128 * 128 * 2 + 255) // 256 * 256
     # ... and in a batch, as wide as the batch's largest problem.
     b2 = B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 1000], B.DPP_PREC_SPLIT_BF16)
     f2 = B.dpp_workspace_size_batched(True, B.DPP_F64, [100, 1000], B.DPP_PREC_FP64)
-    assert b2 - f2 == sum((4 * n * 1024 * 2 + 255) // 256 * 256 for n in (100, 1000))
+    assert b2 - f2 == sum((4 * ((n + 31) // 32 * 32) * 1024 * 2 + 255) // 256 * 256 for n in (100, 1000))
     assert B.dpp_workspace_size(True, B.DPP_F64, (1 << 20) + 1, B.DPP_PREC_FP64) == 0
 
 
