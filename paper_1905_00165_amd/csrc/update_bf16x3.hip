@@ -68,10 +68,10 @@ struct Shape {
     static_assert(KC == 16 || KC == 32, "rows of 32 or 64 bytes");
     static_assert(kKAlign % KC == 0, "stages must tile every k range");
     static_assert(BUF % (1024 * NW) == 0, "copies must split evenly over wavefronts");
-    static_assert(MFMAS % READS == 0, "interleave needs whole MFMA groups per read");
+    static_assert(KSTEPS == 1 || MFMAS % READS == 0, "interleave needs whole MFMA groups per read");
     static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
 };
-using Wide = Shape<256, 256, 2, 2, 1, 2, 32, 2>;
+using Wide = Shape<256, 256, 2, 4, 1, 1, 16, 4>;
 using Medium = Shape<256, 128, 2, 2, 1, 2, 32, 2>;
 using Narrow = Shape<128, 64, 4, 1, 3, 1, 32, 2>;
 
