@@ -13,8 +13,9 @@
 //
 // Tiling: a 256-thread workgroup owns a 128x128 tile of C; its four wavefronts
 // each own 64x64 as 4x4 blocks of v_mfma_f64_16x16x4f64. K advances in chunks
-// of 16 staged through LDS (k-major, so the column-major source is read with
-// unit stride). For LDL^H only tiles on or below the diagonal are launched.
+// of 16 staged through two LDS buffers (k-major, so the column-major source is
+// read with unit stride); the next chunk's loads are in flight while the
+// current one is multiplied. For LDL^H only tiles on or below the diagonal are launched.
 // Workgroup b runs tile (b % 8) * (G / 8) + b / 8 (G, the grid size, is a
 // multiple of 8), so each XCD takes a contiguous range of tiles.
 #include "dpp_internal.h"
@@ -59,7 +60,7 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t NR, int64_t NC, bool 
 }
 
 template <typename T, bool HERM>
-__global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ probs, Region rg,
+__global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__ probs, Region rg,
                                                   int64_t k0, int kw)
 {
     const DevProb P = probs[blockIdx.y];
@@ -79,8 +80,10 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
     const int64_t lda = P.lda;
     const double* __restrict__ piv = P.piv;
 
-    __shared__ double sA[KC][TM + PAD];
-    __shared__ double sB[KC][TN + PAD];
+    // Two LDS buffers: chunk c + 1 is loaded into registers while chunk c is
+    // multiplied, then stored to the other buffer; one barrier per chunk.
+    __shared__ double sA[2][KC][TM + PAD];
+    __shared__ double sB[2][KC][TN + PAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -96,48 +99,65 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
     const int64_t rowA0 = rg.r0 + tc.i0;  // global row of tile row 0
     const int64_t colB0 = rg.c0 + tc.j0;  // global col of tile col 0
 
-    for (int kc = 0; kc < kw; kc += KC) {
-        // A tile: rows rowA0 + i, k = k0 + kc + kk. Thread -> (i = tid % 128, kk = tid/128 + 2q).
+    // Register staging of one chunk. A: thread -> (i = tid % 128, kk = tid/128 + 2q).
+    // B (LDL^H): (j = tid % 128, kk = tid/128 + 2q), B[k][c] = L[c][k] * d'_k.
+    // B (LU): (kk = tid % 16, j = tid/16 + 16q), B[k][c] = U[k][c] = A[k][c].
+    double ra[KC / 2], rb[KC / 2];
+    auto load_chunk = [&](int kc) {
         {
             const int i = tid & (TM - 1);
             const int64_t gr = rowA0 + i;
 #pragma unroll
             for (int q = 0; q < KC / 2; ++q) {
-                const int kk = (tid >> 7) + 2 * q;
-                const int64_t gk = k0 + kc + kk;
-                sA[kk][i] = (gr < rEnd) ? (double)A[gr + gk * lda] : 0.0;
+                const int64_t gk = k0 + kc + (tid >> 7) + 2 * q;
+                ra[q] = (gr < rEnd) ? (double)A[gr + gk * lda] : 0.0;
             }
         }
         if constexpr (HERM) {
-            // B[k][c] = L[c][k] * d'_k with L in the lower triangle of A.
             const int j = tid & (TN - 1);
             const int64_t gc = colB0 + j;
 #pragma unroll
             for (int q = 0; q < KC / 2; ++q) {
-                const int kk = (tid >> 7) + 2 * q;
-                const int64_t gk = k0 + kc + kk;
-                sB[kk][j] = (gc < cEnd) ? (double)A[gc + gk * lda] * piv[gk] : 0.0;
+                const int64_t gk = k0 + kc + (tid >> 7) + 2 * q;
+                rb[q] = (gc < cEnd) ? (double)A[gc + gk * lda] * piv[gk] : 0.0;
             }
         } else {
-            // B[k][c] = U[k][c] = A[k][c]: for a column, KC consecutive k.
-            const int kk = tid & (KC - 1);
-            const int64_t gk = k0 + kc + kk;
+            const int64_t gk = k0 + kc + (tid & (KC - 1));
 #pragma unroll
             for (int q = 0; q < TN / 16; ++q) {
-                const int j = (tid >> 4) + 16 * q;
-                const int64_t gc = colB0 + j;
-                sB[kk][j] = (gc < cEnd) ? (double)A[gk + gc * lda] : 0.0;
+                const int64_t gc = colB0 + (tid >> 4) + 16 * q;
+                rb[q] = (gc < cEnd) ? (double)A[gk + gc * lda] : 0.0;
             }
         }
-        __syncthreads();
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < KC / 2; ++q) sA[buf][(tid >> 7) + 2 * q][tid & (TM - 1)] = ra[q];
+        if constexpr (HERM) {
+#pragma unroll
+            for (int q = 0; q < KC / 2; ++q) sB[buf][(tid >> 7) + 2 * q][tid & (TN - 1)] = rb[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < TN / 16; ++q) sB[buf][tid & (KC - 1)][(tid >> 4) + 16 * q] = rb[q];
+        }
+    };
+    static_assert(TN / 16 == KC / 2, "B staging uses KC/2 registers in both forms");
+
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    const int nchunks = kw / KC;
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunks) load_chunk((ch + 1) * KC);
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
             double af[4], bf[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                af[b] = sA[kk][wm * 64 + b * 16 + (lane & 15)];
-                bf[b] = sB[kk][wn * 64 + b * 16 + (lane & 15)];
+                af[b] = sA[buf][kk][wm * 64 + b * 16 + (lane & 15)];
+                bf[b] = sB[buf][kk][wn * 64 + b * 16 + (lane & 15)];
             }
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
@@ -146,6 +166,9 @@ __global__ __launch_bounds__(256) void update_f64(const DevProb* __restrict__ pr
                     acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], acc[bi][bj],
                                                                        0, 0, 0);
         }
+        // The other buffer was last read in chunk ch - 1, before the barrier
+        // that ended it.
+        if (ch + 1 < nchunks) store_chunk(buf ^ 1);
         __syncthreads();
     }
 
