@@ -126,14 +126,16 @@ typedef struct {
 /*
  * dpp_sample_ldlh_batched / dpp_sample_lu_batched - `count` independent
  * problems, each with its own n, lda, stream of uniforms and outputs, sampled
- * by one launch sequence on `stream` (each step of the factorization is one
- * launch covering every problem that still has that step).
+ * by one launch sequence on `stream`: the problems are sorted by size into
+ * groups, and each step of a group's factorization is one launch covering
+ * every problem of the group that still has that step.
  *   probs   HOST array of `count` descriptors; it is read before the call
  *           returns and may be reused at once.
  *   ws      device workspace of dpp_workspace_size_batched(...) bytes.
  * Every problem's results equal those of the single call on that problem
- * (bit for bit): the blocking depends only on (dtype, precision), and the
- * problems do not interact. Problems must not share A or output buffers.
+ * (bit for bit): the blocking depends only on (dtype, precision), never on
+ * the other problems, and the problems do not interact. Problems must not
+ * share A or output buffers.
  */
 dpp_status dpp_sample_ldlh_batched(const dpp_problem* probs, int64_t count, dpp_dtype dt,
                                    dpp_precision prec, void* ws, size_t ws_bytes, void* stream);
@@ -144,6 +146,19 @@ dpp_status dpp_sample_lu_batched(const dpp_problem* probs, int64_t count, dpp_dt
    array). Returns 0 for invalid arguments. */
 size_t dpp_workspace_size_batched(int hermitian, dpp_dtype dt, const int64_t* ns, int64_t count,
                                   dpp_precision prec);
+
+/*
+ * dpp_copy_lower - stage a working copy for dpp_sample_ldlh: copy the lower
+ * triangle (with the diagonal) of the n x n column-major matrix src (leading
+ * dimension ld_src) into dst (ld_dst). The in-place LDL^H sampler (Sec. 3,
+ * Hermitian form) reads and overwrites only that triangle, so this restores a
+ * working copy from K at half the bytes of a full copy; dst's strict upper
+ * triangle is left as it was. Both are device buffers of storage type dt;
+ * they must not overlap. Asynchronous on `stream`; argument errors (n < 1,
+ * ld < n or > 2^20, NULL pointers, bad dt) return before any launch.
+ */
+dpp_status dpp_copy_lower(void* dst, const void* src, dpp_dtype dt, int64_t n, int64_t ld_dst,
+                          int64_t ld_src, void* stream);
 
 /* Static, NUL-terminated description of a status code. */
 const char* dpp_status_string(dpp_status s);

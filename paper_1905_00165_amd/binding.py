@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
     L.dpp_workspace_size_batched.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64),
                                              _i64, ctypes.c_int]
     L.dpp_workspace_size_batched.restype = ctypes.c_size_t
+    L.dpp_copy_lower.argtypes = [_vp, _vp, ctypes.c_int, _i64, _i64, _i64, _vp]
+    L.dpp_copy_lower.restype = ctypes.c_int
     L.dpp_status_string.argtypes = [ctypes.c_int]
     L.dpp_status_string.restype = ctypes.c_char_p
     L.dpp_profile_begin.argtypes = []
@@ -79,6 +81,20 @@ def lib() -> ctypes.CDLL:
 
 def dpp_status_string(status: int) -> str:
     return lib().dpp_status_string(int(status)).decode()
+
+
+def dpp_copy_lower(dst, src):
+    """Copy the lower triangle (with the diagonal) of src into dst: both
+    column-major n x n device tensors of one dtype (a working copy for
+    dpp_sample_ldlh). Asynchronous on the current stream."""
+    n, ldd = _check_matrix(dst)
+    m, lds = _check_matrix(src)
+    if m != n or _dtype_code(src) != _dtype_code(dst):
+        raise ValueError("dst and src must have the same size and dtype")
+    st = lib().dpp_copy_lower(dst.data_ptr(), src.data_ptr(), _dtype_code(dst), n, ldd, lds,
+                              _stream_handle(dst.device))
+    if st != DPP_OK:
+        raise DppError(st, "dpp_copy_lower")
 
 
 def dpp_workspace_size(hermitian: bool, dtype: int, n: int, prec: int) -> int:

@@ -414,6 +414,20 @@ size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t cou
 
 extern "C" {
 
+dpp_status dpp_copy_lower(void* dst, const void* src, dpp_dtype dt, int64_t n, int64_t ld_dst,
+                          int64_t ld_src, void* stream)
+{
+    if (!dst || !src || n < 1 || ld_dst < n || ld_src < n || ld_dst > kMaxLda || ld_src > kMaxLda ||
+        (dt != DPP_F64 && dt != DPP_F32))
+        return DPP_ERR_INVALID_ARG;
+    const dpp_status dev = device_ok();
+    if (dev != DPP_OK) return dev;
+    if (dpp::launch_copy_lower(dt == DPP_F64 ? 0 : 1, dst, src, n, ld_dst, ld_src,
+                               static_cast<hipStream_t>(stream)) != hipSuccess)
+        return DPP_ERR_HIP;
+    return DPP_OK;
+}
+
 dpp_status dpp_sample_ldlh(void* A, dpp_dtype dt, int64_t n, int64_t lda, const double* u,
                            uint8_t* mask, double* pivots, double* loglik, int32_t* info,
                            dpp_precision prec, void* ws, size_t ws_bytes, void* stream)

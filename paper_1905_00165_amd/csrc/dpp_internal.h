@@ -86,6 +86,8 @@ hipError_t launch_finalize(const DevProb* probs, int nprob, hipStream_t s);
 
 // Copies the factored diagonal blocks from each problem's strip into A (lower
 // part for LDL^H, whole block for LU).
+hipError_t launch_copy_lower(int dtype, void* dst, const void* src, int64_t n, int64_t ldd,
+                             int64_t lds, hipStream_t s);
 hipError_t launch_store_diag(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
                              hipStream_t s);
 

@@ -86,6 +86,16 @@ def test_argument_errors_return_before_any_launch(name):
     assert f(p, 0, 10, 10, p, p, p, p, p, 1, ws, 16, None) == 2
 
 
+def test_copy_lower_argument_errors():
+    f = B.lib().dpp_copy_lower
+    p = ctypes.c_void_p(0x1000)
+    assert f(None, p, 0, 10, 10, 10, None) == 1
+    assert f(p, p, 0, 0, 10, 10, None) == 1
+    assert f(p, p, 0, 10, 9, 10, None) == 1
+    assert f(p, p, 0, 10, 10, (1 << 20) + 1, None) == 1
+    assert f(p, p, 7, 10, 10, 10, None) == 1
+
+
 def test_batched_argument_errors():
     lib = B.lib()
     p = 0x1000

@@ -332,3 +332,28 @@ def test_batched_lensembles_uneven_n_fp32(prec):
         torch.cuda.synchronize()
         assert torch.equal(single["mask"], outs[i]["mask"])
         assert torch.equal(single["pivots"], outs[i]["pivots"])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_copy_lower_stages_the_triangle(dtype):
+    """dpp_copy_lower copies the lower triangle with the diagonal, leaves the
+    strict upper triangle of the destination alone, and a sample from the
+    staged copy equals a sample from a full copy (ragged n, padded lda)."""
+    n, lda = 1000, 1037
+    K = W.hermitian_kernel(n, seed=140)
+    buf = torch.empty(lda * n, dtype=dtype, device=DEV)
+    src = torch.as_strided(buf, (n, n), (1, lda))
+    src.copy_(torch.from_numpy(K))
+    dst = B.colmajor(torch.full((n, n), -7.0, dtype=dtype), device=DEV)
+    B.dpp_copy_lower(dst, src)
+    torch.cuda.synchronize()
+    d, sK = dst.cpu().numpy(), src.cpu().numpy()
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(d[low], sK[low])
+    assert np.all(d[~low] == -7.0)
+    u = torch.from_numpy(W.uniform_stream(n, seed=14000)).to(DEV)
+    full = src.clone()
+    a = B.dpp_sample_ldlh(dst, u, prec=1)
+    b = B.dpp_sample_ldlh(full, u, prec=1)
+    torch.cuda.synchronize()
+    assert torch.equal(a["mask"], b["mask"]) and torch.equal(a["pivots"], b["pivots"])
