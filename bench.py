@@ -49,6 +49,9 @@ def parse():
                         "(lets profiled runs skip the QR of the generator)")
     p.add_argument("--prepare-only", action="store_true",
                    help="generate (and cache) K, then exit")
+    p.add_argument("--streams", type=int, default=1,
+                   help="split each step's samples over this many concurrent batched calls, "
+                        "one per stream (forked and joined inside the step)")
     p.add_argument("--no-graph", action="store_true",
                    help="launch every step eagerly instead of replaying a captured HIP graph")
     p.add_argument("--extra", type=int, default=1,
@@ -61,7 +64,9 @@ def run_path(torch, B, K, us, prec, args, As, ws):
     """Warm up, then time `args.steps` steps; returns timing and profile.
 
     A step restores each sample's working copy from K (its lower triangle,
-    all the LDL^H sampler reads and writes) and runs one batched call. By default one step is captured in a HIP graph and the timed steps
+    all the LDL^H sampler reads and writes) and runs one batched call (or,
+    with --streams S, S concurrent batched calls over the samples, one per
+    stream). By default one step is captured in a HIP graph and the timed steps
     replay it (the launch list of a call depends only on the sizes, so every
     replay does the full work on the same buffers); the per-kernel event
     profile then comes from one eager step after the timed region."""
@@ -73,11 +78,30 @@ def run_path(torch, B, K, us, prec, args, As, ws):
              "info": torch.empty(1, dtype=torch.int32, device=dev)} for _ in As]
 
     Kc = K.t()  # column-major view (K is symmetric)
+    S = max(1, min(args.streams, len(As)))
+    groups = [list(range(g, len(As), S)) for g in range(S)]
+    streams = [torch.cuda.Stream() for _ in range(S)] if S > 1 else []
+    wss = [ws] if S == 1 else [
+        torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, [n] * len(g), prec),
+                    dtype=torch.uint8, device=dev) for g in groups]
+
+    def call(g, w):
+        for i in g:
+            B.dpp_copy_lower(As[i].t(), Kc)  # the sampler touches the lower triangle only
+        B.dpp_sample_ldlh_batched([As[i].t() for i in g], [us[i] for i in g], prec=prec, ws=w,
+                                  outs=[outs[i] for i in g])
 
     def step():
-        for A in As:
-            B.dpp_copy_lower(A.t(), Kc)  # the sampler touches the lower triangle only
-        B.dpp_sample_ldlh_batched([A.t() for A in As], us, prec=prec, ws=ws, outs=outs)
+        if S == 1:
+            call(groups[0], wss[0])
+            return
+        main = torch.cuda.current_stream()
+        for st, g, w in zip(streams, groups, wss):
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                call(g, w)
+        for st in streams:
+            main.wait_stream(st)
 
     for _ in range(args.warmup):
         step()

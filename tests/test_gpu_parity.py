@@ -357,3 +357,20 @@ def test_copy_lower_stages_the_triangle(dtype):
     b = B.dpp_sample_ldlh(full, u, prec=1)
     torch.cuda.synchronize()
     assert torch.equal(a["mask"], b["mask"]) and torch.equal(a["pivots"], b["pivots"])
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_greedy_ml_mode(prec):
+    """Greedy maximum-likelihood selection is the same sampler with u = 1/2
+    for every index (keep j iff its conditional inclusion probability exceeds
+    1/2): the GPU's decisions and pivots match the oracle's under that stream."""
+    n = 700
+    K = W.hermitian_kernel(n, seed=150)
+    u = np.full(n, 0.5)
+    t, h = TOL[prec]
+    ref = oracle.ldlh(K, u)
+    got = _run(True, K, u, prec)
+    v = compare(got["mask"], got["pivots"], got["loglik"], ref, u, t, h)
+    assert v.ok or v.near_tie, v.why
+    d = got["pivots"] + 1.0 - got["mask"]
+    assert np.array_equal(got["mask"], (d > 0.5).astype(np.uint8))
