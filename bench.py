@@ -3,8 +3,9 @@
 Workload: K = Q_r Q_r^T, Q_r the Q factor of QR of a seeded N(0,1) n x r matrix
 (n = 16384, r = 4096), FP64 storage; every sample has its own seeded uniform
 stream and must have |Y| = r. A step samples `batch` independent samples of K
-in one batched LDL^H call (dpp_sample_ldlh_batched), after restoring each
-sample's working copy of K (the factorization runs in place). The headline
+in one batched LDL^H call (dpp_sample_ldlh_batched) that reads the resident K
+and writes each sample's factor to a buffer of its own (out of place: no
+per-sample copy of K). The headline
 `value` is the split-BF16 path's samples/s over the timed steps; the plain FP64
 path is timed the same way and reported beside it.
 
@@ -63,10 +64,9 @@ def parse():
 def run_path(torch, B, K, us, prec, args, As, ws):
     """Warm up, then time `args.steps` steps; returns timing and profile.
 
-    A step restores each sample's working copy from K (its lower triangle,
-    all the LDL^H sampler reads and writes) and runs one batched call (or,
-    with --streams S, S concurrent batched calls over the samples, one per
-    stream). By default one step is captured in a HIP graph and the timed steps
+    A step runs one batched call (or, with --streams S, S concurrent batched
+    calls over the samples, one per stream) that reads K in place of a working
+    copy and writes each sample's factor to its own buffer. By default one step is captured in a HIP graph and the timed steps
     replay it (the launch list of a call depends only on the sizes, so every
     replay does the full work on the same buffers); the per-kernel event
     profile then comes from one eager step after the timed region."""
@@ -86,10 +86,8 @@ def run_path(torch, B, K, us, prec, args, As, ws):
                     dtype=torch.uint8, device=dev) for g in groups]
 
     def call(g, w):
-        for i in g:
-            B.dpp_copy_lower(As[i].t(), Kc)  # the sampler touches the lower triangle only
         B.dpp_sample_ldlh_batched([As[i].t() for i in g], [us[i] for i in g], prec=prec, ws=w,
-                                  outs=[outs[i] for i in g])
+                                  outs=[outs[i] for i in g], Ks=[Kc] * len(g))
 
     def step():
         if S == 1:
@@ -245,7 +243,7 @@ def graph_time(torch, step, reps, warmup=1):
 
 def bench_plain(torch, B, W, dev, cpu):
     """One sample of a dense Hermitian K, n = 1024 (FP64 storage), both paths:
-    latency per sample (restore + call, graph replay); with `cpu`, the oracle's
+    latency per sample (one out-of-place call, graph replay); with `cpu`, the oracle's
     time for the whole sample on the host cores as its CPU baseline."""
     n = 1024
     Kh = W.hermitian_kernel(n, seed=1)
@@ -256,15 +254,15 @@ def bench_plain(torch, B, W, dev, cpu):
     out = {"workload": "K = Q diag(lam) Q^T, Q from QR of N(0,1) 1024x1024, lam ~ U(0,1); "
                        "one sample, FP64 storage, LDL^H", "n": n}
     for name, prec in (("split", B.DPP_PREC_SPLIT_BF16), ("fp64", B.DPP_PREC_FP64)):
-        ws = torch.empty(B.dpp_workspace_size(True, B.DPP_F64, n, prec), dtype=torch.uint8, device=dev)
+        ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, [n], prec), dtype=torch.uint8,
+                         device=dev)
         o = {"mask": torch.empty(n, dtype=torch.uint8, device=dev),
              "pivots": torch.empty(n, dtype=torch.float64, device=dev),
              "loglik": torch.empty(1, dtype=torch.float64, device=dev),
              "info": torch.empty(1, dtype=torch.int32, device=dev)}
 
         def step():
-            A.copy_(K)
-            B.dpp_sample_ldlh(A, u, prec=prec, ws=ws, out=o)
+            B.dpp_sample_ldlh_batched([A], [u], prec=prec, ws=ws, outs=[o], Ks=[K])
 
         ms = graph_time(torch, step, reps=50)
         out[name] = {"ms_per_sample": round(ms, 4), "samples_per_s": round(1e3 / ms, 1),
@@ -284,7 +282,7 @@ def bench_plain(torch, B, W, dev, cpu):
 def bench_lu(torch, B, W, dev, cpu_seconds):
     """Non-Hermitian K = S H S^-1, n = 8192 (FP64 storage), 32 samples (four
     batched calls of 8, each sample with its own stream), both paths, timed as
-    one graph replay of the four calls with their restores. TFLOP/s counts
+    one graph replay of the four out-of-place calls. TFLOP/s counts
     2n^3/3 per sample. Checks: every info = 0; sample 0's mask equals the
     LDL^H mask of H on the same stream (Prop. 2)."""
     n, per_call, calls = 8192, 8, 4
@@ -306,10 +304,9 @@ def bench_lu(torch, B, W, dev, cpu_seconds):
 
         def step():
             for c in range(calls):
-                for A in As:
-                    A.copy_(K)
                 B.dpp_sample_lu_batched(As, streams[c * per_call:(c + 1) * per_call], prec=prec,
-                                        ws=ws, outs=outs[c * per_call:(c + 1) * per_call])
+                                        ws=ws, outs=outs[c * per_call:(c + 1) * per_call],
+                                        Ks=[K] * per_call)
 
         ms = graph_time(torch, step, reps=2)
         sizes = [int(o["mask"].sum().item()) for o in outs]
@@ -353,7 +350,7 @@ def bench_lu(torch, B, W, dev, cpu_seconds):
 def bench_lensemble(torch, B, W, dev, count=4096):
     """`count` L-ensemble marginal kernels, n_i ~ U{64..1024}, rank 64, formed in
     FP64 and stored FP32, one sample each in one batched LDL^H call, both paths,
-    timed as a graph replay of (restore of all working copies + the call).
+    timed as a graph replay of the out-of-place call.
     TFLOP/s counts sum n_i^3/3. Checks: every info = 0 and |Y_i| <= 64."""
     ns = W.lensemble_batch_sizes(count, seed=4)
     offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
@@ -389,8 +386,7 @@ def bench_lensemble(torch, B, W, dev, count=4096):
                          dtype=torch.uint8, device=dev)
 
         def step():
-            Aflat.copy_(Kflat)
-            B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, outs=outs)
+            B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, outs=outs, Ks=Ks)
 
         ms = graph_time(torch, step, reps=3)
         sizes = np.array([int(x) for x in torch.stack([o["mask"].sum() for o in outs]).cpu()])

@@ -111,7 +111,18 @@ dpp_status dpp_sample_lu(void* A, dpp_dtype dt, int64_t n, int64_t lda, const do
 size_t dpp_workspace_size(int hermitian, dpp_dtype dt, int64_t n, dpp_precision prec);
 
 /* One problem of a batched call. All pointers are device pointers; the fields
-   mean what the arguments of the same names mean for the single calls. */
+   A ... info mean what the arguments of the same names mean for the single
+   calls.
+     K, ldk  out-of-place source (optional). K NULL (or K == A with ldk == lda):
+             in place, A holds K on entry. Otherwise K is the n x n kernel with
+             leading dimension ldk (n <= ldk <= 2^20), read only, in storage
+             disjoint from A (checked; DPP_ERR_INVALID_ARG otherwise); A is
+             then an output only: its contents on entry are ignored and on exit
+             it holds the factor exactly as the in-place call would leave it
+             (bit for bit), except that for LDL^H the strict upper triangle of
+             A is not written. Each entry of K is read once, so no working copy
+             of K is needed per sample. Several problems may share one K; no
+             problem's A may overlap another problem's A or K. */
 typedef struct {
     void* A;
     int64_t n;
@@ -121,6 +132,8 @@ typedef struct {
     double* pivots;
     double* loglik;
     int32_t* info;
+    const void* K;
+    int64_t ldk;
 } dpp_problem;
 
 /*

@@ -31,7 +31,7 @@ class DppError(RuntimeError):
 
 class dpp_problem(ctypes.Structure):
     _fields_ = [("A", _vp), ("n", _i64), ("lda", _i64), ("u", _vp), ("mask", _vp),
-                ("pivots", _vp), ("loglik", _vp), ("info", _vp)]
+                ("pivots", _vp), ("loglik", _vp), ("info", _vp), ("K", _vp), ("ldk", _i64)]
 
 
 class dpp_kernel_stats(ctypes.Structure):
@@ -210,10 +210,12 @@ def dpp_sample_lu(A, u, prec=DPP_PREC_FP64, ws=None, out=None):
     return _single("dpp_sample_lu", False, A, u, prec, ws, out)
 
 
-def _batched(name, hermitian, As, us, prec, ws, outs):
+def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None):
     torch = _torch()
     if len(As) != len(us) or not As:
         raise ValueError("need matching, non-empty lists of matrices and streams")
+    if Ks is not None and len(Ks) != len(As):
+        raise ValueError("Ks needs one source matrix (or None) per problem")
     dt = _dtype_code(As[0])
     probs = (dpp_problem * len(As))()
     res = []
@@ -224,10 +226,17 @@ def _batched(name, hermitian, As, us, prec, ws, outs):
             raise ValueError("all matrices of a batch share one dtype")
         if u.dtype != torch.float64 or u.numel() < n or not u.is_contiguous():
             raise ValueError("each u must be a contiguous float64 device tensor with >= n entries")
+        kp, ldk = None, 0
+        K = Ks[i] if Ks is not None else None
+        if K is not None:
+            nk, ldk = _check_matrix(K)
+            if nk != n or _dtype_code(K) != dt or K.device != A.device:
+                raise ValueError("each K must match its A in size, dtype and device")
+            kp = K.data_ptr()
         o = _outputs(n, A.device, outs[i] if outs else None)
         probs[i] = dpp_problem(A.data_ptr(), n, lda, u.data_ptr(), o["mask"].data_ptr(),
                                o["pivots"].data_ptr(), o["loglik"].data_ptr(),
-                               o["info"].data_ptr())
+                               o["info"].data_ptr(), kp, ldk)
         res.append(o)
         ns.append(n)
     need = dpp_workspace_size_batched(hermitian, dt, ns, prec)
@@ -240,11 +249,14 @@ def _batched(name, hermitian, As, us, prec, ws, outs):
     return res
 
 
-def dpp_sample_ldlh_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None):
-    """Independent symmetric problems in one launch sequence."""
-    return _batched("dpp_sample_ldlh_batched", True, As, us, prec, ws, outs)
+def dpp_sample_ldlh_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=None):
+    """Independent symmetric problems in one launch sequence. With Ks (one
+    column-major source per problem, or None for in place), each K is read
+    only and its A receives the factor (lower triangle)."""
+    return _batched("dpp_sample_ldlh_batched", True, As, us, prec, ws, outs, Ks)
 
 
-def dpp_sample_lu_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None):
-    """Independent general problems in one launch sequence."""
-    return _batched("dpp_sample_lu_batched", False, As, us, prec, ws, outs)
+def dpp_sample_lu_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=None):
+    """Independent general problems in one launch sequence; Ks as for
+    dpp_sample_ldlh_batched."""
+    return _batched("dpp_sample_lu_batched", False, As, us, prec, ws, outs, Ks)

@@ -311,6 +311,19 @@ dpp_status run_group(const Ctx& c)
     return timed(c, K_FINALIZE, 0.0, 0.0, [&] { return dpp::launch_finalize(c.probs, c.count, c.s); });
 }
 
+// An out-of-place problem's K: a valid leading dimension, and either A itself
+// with the same leading dimension (in place) or storage disjoint from A's.
+bool source_ok(const dpp_problem& q, dpp_dtype dt)
+{
+    if (q.ldk < q.n || q.ldk > kMaxLda) return false;
+    if (q.K == q.A) return q.ldk == q.lda;
+    const uintptr_t elt = dt == DPP_F64 ? 8 : 4;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(q.A), k0 = reinterpret_cast<uintptr_t>(q.K);
+    const uintptr_t a1 = a0 + (uintptr_t)((q.n - 1) * q.lda + q.n) * elt;
+    const uintptr_t k1 = k0 + (uintptr_t)((q.n - 1) * q.ldk + q.n) * elt;
+    return a1 <= k0 || k1 <= a0;
+}
+
 dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
                dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
 {
@@ -321,6 +334,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         if (q.n < 1 || q.lda < q.n || q.lda > kMaxLda || !q.A || !q.u || !q.mask || !q.pivots ||
             !q.loglik || !q.info)
             return DPP_ERR_INVALID_ARG;
+        if (q.K && !source_ok(q, dt)) return DPP_ERR_INVALID_ARG;
         nmax = q.n > nmax ? q.n : nmax;
     }
     const Plan plan = make_plan(herm, dt, prec, nmax);
@@ -354,6 +368,8 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.A = q.A;
         d.n = q.n;
         d.lda = q.lda;
+        d.K = q.K ? q.K : q.A;
+        d.ldk = q.K ? q.ldk : q.lda;
         d.u = q.u;
         d.mask = q.mask;
         d.piv = q.pivots;

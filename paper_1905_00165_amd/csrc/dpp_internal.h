@@ -16,6 +16,8 @@ struct DevProb {
     void* A;          // column-major n x n, lda, storage type T
     int64_t n;
     int64_t lda;
+    const void* K;    // the kernel, leading dimension ldk: read where an entry is
+    int64_t ldk;      // read first (first_source below); K == A in place
     const double* u;  // n uniforms
     uint8_t* mask;    // n
     double* piv;      // n, pivots after the decision
@@ -25,6 +27,20 @@ struct DevProb {
     double* diag;     // ceil(n/64) factored 64x64 diagonal blocks, column-major,
                       // block b at diag[b * 64 * 64]; copied into A at the end
 };
+
+// Out-of-place calls put the factor in A and leave K untouched. Every entry
+// the factorization uses (the lower triangle for LDL^H, all of it for LU) is
+// first read by exactly one launch: the diagonal-block launch at column 0 (its
+// block, the panel below it and, for LU, the rows of U to its right), or an
+// update whose factored columns start at k0 = 0 (the launch sequence gives
+// each such update columns no earlier launch has touched). Those launches read
+// K and write A; every other launch reads and writes A. In place, K is A.
+template <typename T>
+__device__ __forceinline__ const T* first_source(const DevProb& P, bool first, int64_t& ld)
+{
+    ld = first ? P.ldk : P.lda;
+    return first ? static_cast<const T*>(P.K) : static_cast<const T*>(P.A);
+}
 
 // Split-BF16 panel copies of a problem: four planes q = 0: hi(L), 1: lo(L),
 // 2: hi(B), 3: lo(B), entry (r, kk) with r the global row of L (or the global
@@ -93,7 +109,7 @@ hipError_t launch_store_diag(bool herm, int dtype, const DevProb* probs, int npr
 
 // Copy `cnt` (<= kDescPerLaunch) host descriptors to dst through the kernel
 // argument block of a one-workgroup launch.
-constexpr int kDescPerLaunch = 44;
+constexpr int kDescPerLaunch = 36;  // 36 descriptors + count fit the 4 KiB argument block
 hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStream_t s);
 
 }  // namespace dpp

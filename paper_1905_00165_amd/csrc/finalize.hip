@@ -65,6 +65,7 @@ struct DescChunk {
     DevProb d[kDescPerLaunch];
     int cnt;
 };
+static_assert(sizeof(DescChunk) <= 4096, "kernel arguments are limited to 4 KiB");
 
 __global__ void store_descs(DescChunk chunk, DevProb* __restrict__ dst)
 {

@@ -38,6 +38,8 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
+    int64_t lds;  // leading dimension of the source the loads read (K at column 0)
+    const T* __restrict__ S = first_source<T>(P, c0 == 0, lds);
 
     // One LDS array carved by hand so that sB sits at address 0: the chain's
     // 64-entry broadcast reads then all use one base register and immediate
@@ -58,10 +60,10 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
         {
             // Buffer loads: the column offset is a scalar, so the 64 loads
             // share one address register; reads past the end of A return 0.
-            const int64_t base = c0 + c0 * lda;
+            const int64_t base = c0 + c0 * lds;
             const __amdgpu_buffer_rsrc_t rb =
-                strip_rsrc(A + base, ((n - 1) * lda + n - base) * (int64_t)sizeof(T));
-            const int cs = (int)(lda * (int64_t)sizeof(T));
+                strip_rsrc(S + base, ((n - 1) * lds + n - base) * (int64_t)sizeof(T));
+            const int cs = (int)(lds * (int64_t)sizeof(T));
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 const double v = buf_load<T>(rb, lane * (int)sizeof(T), k * cs);
@@ -128,32 +130,35 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
     const int64_t wrow0 = row0 + (int64_t)(tid >> 6) * (kGroups * 16);
     if (wrow0 >= n) return;
 
-    // Strip = columns [c0, c0+64) from row wrow0 on; lane (q, i16) of group g
-    // reads row wrow0 + 16g + i16 of columns q + 4e + 16b.
+    // Strip = columns [c0, c0+64) from row wrow0 on, read from S and written
+    // to A; lane (q, i16) of group g reads row wrow0 + 16g + i16 of columns
+    // q + 4e + 16b.
     const __amdgpu_buffer_rsrc_t rs =
         strip_rsrc(A + wrow0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rsi =
+        strip_rsrc(S + wrow0 + c0 * lds, (int64_t)L * lds * (int64_t)sizeof(T));
     const int cstride = (int)(lda * (int64_t)sizeof(T));
+    const int istride = (int)(lds * (int64_t)sizeof(T));
     const int ngroups = (int)((n - wrow0 + 15) / 16) < kGroups ? (int)((n - wrow0 + 15) / 16) : kGroups;
 
-    auto voff_of = [&](int g) {
+    auto row_of = [&](int g) {
         const int64_t r = wrow0 + 16 * g + i16;
-        const int rr = (int)((r < n ? r : n - 1) - wrow0);  // tail rows re-read the last row
-        return rr * (int)sizeof(T) + q * cstride;
+        return (int)((r < n ? r : n - 1) - wrow0) * (int)sizeof(T);  // tail rows re-read the last row
     };
     double nxt[16];
     {
-        const int v = voff_of(0);
+        const int v = row_of(0) + q * istride;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+        for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rsi, v, 4 * k * istride);
     }
     for (int g = 0; g < ngroups; ++g) {
         double cur[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
         if (g + 1 < ngroups) {
-            const int v = voff_of(g + 1);
+            const int v = row_of(g + 1) + q * istride;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+            for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rsi, v, 4 * k * istride);
         }
         d4 x[4];
         solve_group(sL, sI, cur, x, q, i16);  // W = A21 L11^{-T}
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
             __builtin_amdgcn_wave_barrier();
         }
         if (r < n) {
-            const int v = voff_of(g);
+            const int v = row_of(g) + q * cstride;
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll

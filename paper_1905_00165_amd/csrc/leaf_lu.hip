@@ -37,6 +37,8 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
+    int64_t lds;  // leading dimension of the source the loads read (K at column 0)
+    const T* __restrict__ S = first_source<T>(P, c0 == 0, lds);
 
     // sT (the tiles) comes first; the chain's broadcast row sB borrows it.
     // The triangles as Tt[t*L + k] = T[k][t] for solve_group: the row panel
@@ -57,10 +59,10 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
         {
             // Buffer loads: the column offset is a scalar, so the 64 loads
             // share one address register; reads past the end of A return 0.
-            const int64_t base = c0 + c0 * lda;
+            const int64_t base = c0 + c0 * lds;
             const __amdgpu_buffer_rsrc_t rb =
-                strip_rsrc(A + base, ((n - 1) * lda + n - base) * (int64_t)sizeof(T));
-            const int cs = (int)(lda * (int64_t)sizeof(T));
+                strip_rsrc(S + base, ((n - 1) * lds + n - base) * (int64_t)sizeof(T));
+            const int cs = (int)(lds * (int64_t)sizeof(T));
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 const double v = buf_load<T>(rb, lane * (int)sizeof(T), k * cs);
@@ -139,6 +141,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
     const int ngroups = (int)((n - w0 + 15) / 16) < kGroups ? (int)((n - w0 + 15) / 16) : kGroups;
     double* const tile = sT + (tid >> 6) * (16 * kTilePitch);
     const int cstride = (int)(lda * (int64_t)sizeof(T));
+    const int istride = (int)(lds * (int64_t)sizeof(T));
 
     // Split planes from the tile: lane l writes row l/4 (of the group),
     // entries 8(l%4) + [0, 8) and 32 + 8(l%4) + [0, 8), 16-byte pieces.
@@ -171,30 +174,31 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
     {
         const __amdgpu_buffer_rsrc_t rs =
             strip_rsrc(A + w0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
-        auto voff_of = [&](int g) {
+        const __amdgpu_buffer_rsrc_t rsi =
+            strip_rsrc(S + w0 + c0 * lds, (int64_t)L * lds * (int64_t)sizeof(T));
+        auto row_of = [&](int g) {
             const int64_t r = w0 + 16 * g + i16;
-            const int rr = (int)((r < n ? r : n - 1) - w0);  // tail rows re-read the last row
-            return rr * (int)sizeof(T) + q * cstride;
+            return (int)((r < n ? r : n - 1) - w0) * (int)sizeof(T);  // tail rows re-read the last row
         };
         double nxt[16];
         {
-            const int v = voff_of(0);
+            const int v = row_of(0) + q * istride;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+            for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rsi, v, 4 * k * istride);
         }
         for (int g = 0; g < ngroups; ++g) {
             double cur[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
             if (g + 1 < ngroups) {
-                const int v = voff_of(g + 1);
+                const int v = row_of(g + 1) + q * istride;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rs, v, 4 * k * cstride);
+                for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rsi, v, 4 * k * istride);
             }
             d4 x[4];
             solve_group(sU, sIU, cur, x, q, i16);  // L21 = A21 U11^{-1}
             if (w0 + 16 * g + i16 < n) {
-                const int v = voff_of(g);
+                const int v = row_of(g) + q * cstride;
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
         const int tcl = lane >> 2, tk = 16 * (lane & 3);
         for (int g = 0; g < ngroups; ++g) {
             const int64_t col = w0 + 16 * g + tcl;
-            const T* src = A + c0 + col * lda + tk;
+            const T* src = S + c0 + col * lds + tk;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
                 tile[tcl * kTilePitch + tk + k] = col < n ? (double)src[k] : 0.0;

@@ -15,14 +15,14 @@
 //
 // Tiling (template Shape): a workgroup owns a TM x TN tile of C split over
 // WR x WC wavefronts, each owning RB x CB blocks of 32x32 (wide shape:
-// 256x256 on 4 wavefronts of 128x128, so each 16-k step reads 16 fragments
-// from LDS and issues 48 MFMAs; narrower shapes serve the narrow updates inside
-// a panel). K advances 32 at a time through two LDS buffers holding the four
-// operand planes. Global -> LDS copies use the gfx950 direct-to-LDS loads
-// (global_load_lds_dwordx4), each instruction writing 1 KiB (16 rows x 64
-// bytes); stage s+1 is in flight while stage s is multiplied, one barrier per
-// stage. LDS rows are 64 bytes with their four 16-byte segments XOR-swizzled by
-// row, so the fragment reads of consecutive rows spread over the banks.
+// 256x256 on 8 wavefronts of 128x64, so each 16-k step reads 12 fragments
+// from LDS and issues 24 MFMAs per wavefront; narrower shapes serve the
+// narrow updates inside a panel). K advances KC (16 or 32) at a time through
+// NST LDS stages holding the four operand planes, NST - 1 of them in flight
+// while one is multiplied, one barrier per stage. Global -> LDS copies use the
+// gfx950 direct-to-LDS loads (global_load_lds_dwordx4), each instruction
+// writing 1 KiB. LDS rows are KC * 2 bytes with their 16-byte segments
+// XOR-swizzled by row (swz below).
 // The MFMA takes the column operand first, so each lane's accumulators map to
 // one row of C and lanes 0-31 cover 32 consecutive rows of a column: the
 // read-modify-write of column-major C is coalesced. Operand rows past the end
@@ -75,13 +75,20 @@ using Wide = Shape<256, 256, 2, 4, 1, 1, 16, 4>;
 using Medium = Shape<256, 128, 2, 2, 1, 2, 32, 2>;
 using Narrow = Shape<128, 64, 4, 1, 3, 1, 32, 2>;
 
-// XOR swizzle of the 16-byte segments of LDS row r, so that the fragment
-// reads of consecutive rows spread over the banks: 64-byte rows (four
-// segments) flip by bits 1-2 of the row, 32-byte rows (two) by bit 2.
+// XOR swizzle of the 16-byte segments of LDS row r. A fragment read (lane l:
+// row l % 32, one segment) is served 16 lanes at a time, 256 bytes over the
+// 64 banks, so the 16 consecutive rows of a group must land on 16 distinct
+// 16-byte bank quads. With 64-byte rows (four segments, four rows per 256
+// bytes) rows r, r+4, r+8, r+12 need four different segment flips: bits 2-3
+// of the row. With 32-byte rows (two segments, eight rows per 256 bytes) rows
+// r and r+8 need different flips: bit 2 xor bit 3. (A flip that spreads only
+// 8 rows leaves half of the LDS cycles as bank conflicts.) The flip uses row
+// bits below 4 only, so it is the same for a row of a plane and for that row
+// inside the 16- or 32-row block one direct-to-LDS copy writes.
 template <int ROWB>
 __device__ __forceinline__ int swz(int r)
 {
-    return ROWB == 64 ? (r >> 1) & 3 : (r >> 2) & 1;
+    return ROWB == 64 ? (r >> 2) & 3 : ((r >> 2) ^ (r >> 3)) & 1;
 }
 
 // s_waitcnt immediate that waits until at most n vector-memory loads of this
@@ -196,6 +203,8 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
+    int64_t lds_;  // leading dimension of the source C is read from (K when k0 == 0)
+    const T* __restrict__ Csrc = first_source<T>(P, k0 == 0, lds_);
 
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
 
@@ -261,6 +270,10 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
         const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
         return A + (rowT0 + i) + (colT0 + jl) * lda;
     };
+    auto c_src = [&](int rb) {
+        const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
+        return Csrc + (rowT0 + i) + (colT0 + jl) * lds_;
+    };
     auto c_ok = [&](int rb, int ju) {
         const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
         const int j = jl + ju;
@@ -276,36 +289,41 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
         (int)(((int64_t)S::TN * lda) * (int64_t)sizeof(T) < 0x7fffffff
                   ? ((int64_t)S::TN * lda) * (int64_t)sizeof(T) : 0x7fffffff),
         kBufFlags);
-    auto c_voff = [&](int rb) {
+    const __amdgpu_buffer_rsrc_t crs_in = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(Csrc) + rowT0 + colT0 * lds_, 0,
+        (int)(((int64_t)S::TN * lds_) * (int64_t)sizeof(T) < 0x7fffffff
+                  ? ((int64_t)S::TN * lds_) * (int64_t)sizeof(T) : 0x7fffffff),
+        kBufFlags);
+    auto c_voff = [&](int rb, int64_t ld) {
         const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
-        return (int)((i + (int64_t)jl * lda) * (int64_t)sizeof(T));
+        return (int)((i + (int64_t)jl * ld) * (int64_t)sizeof(T));
     };
     auto c_load = [&](int r, double (&cv)[CP][16]) {
         const int rb = r / (S::CB / CP), c2 = (r % (S::CB / CP)) * CP;
         if (interior) {
-            const int vo = c_voff(rb);
+            const int vo = c_voff(rb, lds_);
 #pragma unroll
             for (int h = 0; h < CP; ++h)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
-                    cv[h][e] = buf_load_c<T>(crs, vo, (int)(ju * lda * (int64_t)sizeof(T)));
+                    cv[h][e] = buf_load_c<T>(crs_in, vo, (int)(ju * lds_ * (int64_t)sizeof(T)));
                 }
             return;
         }
-        T* const p0 = c_ptr(rb);
+        const T* const p0 = c_src(rb);
 #pragma unroll
         for (int h = 0; h < CP; ++h)
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
-                cv[h][e] = c_ok(rb, ju) ? (double)p0[ju * lda] : 0.0;
+                cv[h][e] = c_ok(rb, ju) ? (double)p0[ju * lds_] : 0.0;
             }
     };
     auto c_store = [&](int r, const double (&cv)[CP][16]) {
         const int rb = r / (S::CB / CP), c2 = (r % (S::CB / CP)) * CP;
         if (interior) {
-            const int vo = c_voff(rb);
+            const int vo = c_voff(rb, lda);
 #pragma unroll
             for (int h = 0; h < CP; ++h)
 #pragma unroll

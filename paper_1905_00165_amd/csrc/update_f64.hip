@@ -78,6 +78,8 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
+    int64_t lds_;  // leading dimension of the source C is read from (K when k0 == 0)
+    const T* __restrict__ Csrc = first_source<T>(P, k0 == 0, lds_);
     const double* __restrict__ piv = P.piv;
 
     // Two LDS buffers: chunk c + 1 is loaded into registers while chunk c is
@@ -180,6 +182,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     for (int bi = 0; bi < 4; ++bi) {
         const int64_t gr = rowA0 + wm * 64 + bi * 16 + (lane & 15);
         T* const rowp = A + gr;
+        const T* const srcp = Csrc + gr;
         // All loads of this 16-row block before any store (see update_bf16x3.hip).
         double cv[4][4];
 #pragma unroll
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
             for (int e = 0; e < 4; ++e) {
                 const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
                 const bool ok = gr < rEnd && gc < cEnd && (!HERM || gr >= gc);
-                cv[bj][e] = ok ? (double)rowp[gc * lda] : 0.0;
+                cv[bj][e] = ok ? (double)srcp[gc * lds_] : 0.0;
             }
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)

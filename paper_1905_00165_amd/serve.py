@@ -3,15 +3,15 @@
 Marginal kernels are registered once and stay resident in HBM. Sample requests
 (kernel id, uniform stream) arrive over time. The server keeps `slots` HIP
 streams; whenever a slot is idle it admits waiting requests, oldest first, as
-long as HBM is available under `mem_budget` for each request's working copy of
-its kernel plus its share of the workspace, and runs them as one batched call on
-that slot's stream. Batches on different slots run concurrently on the device;
+long as HBM is available under `mem_budget` for each request's factor buffer
+plus its share of the workspace, and runs them as one batched call on that
+slot's stream; the call reads the resident kernels out of place (no copy). Batches on different slots run concurrently on the device;
 a slot's memory is released when its completion event has fired, and the next
 waiting requests are admitted as slots and memory free up.
 
 Each request's result equals a standalone call on the same kernel and stream,
 bit for bit: the library's blocking never depends on the other problems of a
-batch, and a batch touches only its own buffers.
+batch, a batch writes only its own buffers, and the kernels are only read.
 
 Host logic only: every sampling step runs in the library's kernels.
 """
@@ -93,15 +93,16 @@ class Server:
 
     # -- accounting ---------------------------------------------------------
     def footprint(self, r):
-        """HBM a request holds while it runs alone: its working copy, its
-        outputs and its workspace (in a batch its split copies can be wider;
-        `batch_cost` charges that)."""
+        """HBM a request holds while it runs alone: its factor buffer (the
+        call reads the resident kernel out of place), its outputs and its
+        workspace (in a batch its split copies can be wider; `batch_cost`
+        charges that)."""
         n = self.kernels[r.kernel].shape[0]
         ws = B.dpp_workspace_size(self.hermitian, self.dtype, n, self.prec)
         return n * n * self.elt + ws + n * 9 + 64
 
     def batch_cost(self, reqs):
-        """HBM of one batched call over `reqs`: working copies, outputs and the
+        """HBM of one batched call over `reqs`: factor buffers, outputs and the
         batch's workspace."""
         if not reqs:
             return 0
@@ -154,12 +155,13 @@ class Server:
             dev = self.kernels[0].device
             with torch.cuda.stream(s.stream):
                 As, us, outs = [], [], []
+                Ks = []
                 for r in take:
                     K = self.kernels[r.kernel]
-                    A = torch.empty_like(K)
-                    A.copy_(K)
+                    A = torch.empty_like(K)   # the factor; K itself is only read
                     n = K.shape[0]
                     As.append(A)
+                    Ks.append(K)
                     us.append(r.u)
                     outs.append({"mask": torch.empty(n, dtype=torch.uint8, device=dev),
                                  "pivots": torch.empty(n, dtype=torch.float64, device=dev),
@@ -170,7 +172,7 @@ class Server:
                                                                   self.prec), 1),
                                  dtype=torch.uint8, device=dev)
                 f = B.dpp_sample_ldlh_batched if self.hermitian else B.dpp_sample_lu_batched
-                f(As, us, prec=self.prec, ws=ws, outs=outs)
+                f(As, us, prec=self.prec, ws=ws, outs=outs, Ks=Ks)
                 ev = torch.cuda.Event()
                 ev.record(s.stream)
             for r in take:

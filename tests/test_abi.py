@@ -106,6 +106,24 @@ def test_batched_argument_errors():
     assert lib.dpp_sample_lu_batched(None, 1, 0, 0, ctypes.c_void_p(p), 1 << 40, None) == 1
 
 
+def test_out_of_place_source_errors():
+    """A source K needs n <= ldk <= 2^20 and storage disjoint from A (K == A
+    with ldk == lda is the in-place call)."""
+    lib = B.lib()
+    p, n = 0x100000, 10
+    ws = ctypes.c_void_p(p)
+
+    def call(K, ldk, lda=n):
+        probs = (B.dpp_problem * 1)(B.dpp_problem(p, n, lda, p, p, p, p, p, K, ldk))
+        return lib.dpp_sample_ldlh_batched(probs, 1, 0, 0, ws, 1 << 40, None)
+
+    assert call(p + 8 * 50, n) == 1              # overlaps A's n x n footprint
+    assert call(p - 8 * 50, n) == 1              # A starts inside K
+    assert call(p + 8 * 200, n - 1) == 1         # ldk < n
+    assert call(p + 8 * 200, (1 << 20) + 1) == 1  # ldk > 2^20
+    assert call(p, n + 1) == 1                   # K == A with another leading dimension
+
+
 def test_profile_without_launches_is_empty():
     B.dpp_profile_begin()
     assert B.dpp_profile_end() == {}

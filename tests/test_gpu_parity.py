@@ -190,6 +190,45 @@ def test_batched_equals_single_bitwise(herm, prec, ns):
         assert np.array_equal(A.cpu().numpy(), single["A"])
 
 
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_out_of_place_equals_in_place(herm, prec):
+    """With a read-only source K per problem (two problems sharing one K, a
+    padded leading dimension on another), each A receives exactly the in-place
+    factor (the lower triangle for LDL^H, whose strict upper triangle of A is
+    left unwritten), the outputs match bit for bit, and K is unchanged."""
+    ns = [700, 700, 1100, 129]
+    Ks = [W.hermitian_kernel(n, seed=60 + i) if herm else W.similarity_kernel(n, seed=60 + i)[0]
+          for i, n in enumerate(ns)]
+    Ks[1] = Ks[0]
+    us = [W.uniform_stream(n, seed=6000 + i) for i, n in enumerate(ns)]
+    src = [B.colmajor(K, device=DEV) for K in Ks]
+    src[1] = src[0]                                   # shared source
+    pad = torch.zeros((ns[2], ns[2] + 3), dtype=torch.float64, device=DEV)
+    pad[:, : ns[2]] = src[2].t()
+    src[2] = pad.t()[: ns[2], :]                      # column-major, ldk = n + 3
+    assert src[2].stride() == (1, ns[2] + 3)
+    before = [s.cpu().numpy().copy() for s in src]
+    As = [torch.full((n, n), float("nan"), dtype=torch.float64, device=DEV).t() for n in ns]
+    uts = [torch.from_numpy(u).to(DEV) for u in us]
+    fb = B.dpp_sample_ldlh_batched if herm else B.dpp_sample_lu_batched
+    outs = fb(As, uts, prec=prec, Ks=src)
+    torch.cuda.synchronize()
+    for i, (K, u, A, o) in enumerate(zip(Ks, us, As, outs)):
+        single = _run(herm, K, u, prec)
+        assert np.array_equal(o["mask"].cpu().numpy(), single["mask"])
+        assert np.array_equal(o["pivots"].cpu().numpy(), single["pivots"])
+        assert float(o["loglik"].cpu()[0]) == single["loglik"]
+        got = A.cpu().numpy()
+        if herm:
+            low = np.tril(np.ones_like(got, dtype=bool))
+            assert np.array_equal(got[low], single["A"][low])
+            assert np.all(np.isnan(got[~low]))
+        else:
+            assert np.array_equal(got, single["A"])
+        assert np.array_equal(src[i].cpu().numpy(), before[i])
+
+
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
 def test_deterministic(prec):
     n = 700

@@ -48,11 +48,13 @@ def test_served_results_equal_standalone_and_overlap(prec):
         u = torch.from_numpy(W.uniform_stream(sizes[k], seed=5_000_000 + i)).to(dev)
         t += float(rng.exponential(2e-4))
         reqs.append(serve.Request(rid=i, kernel=k, u=u, arrival=t))
+    before = [K.clone() for K in kernels]
     torch.cuda.synchronize()
     srv = serve.Server(kernels, prec=prec, slots=3, mem_budget=1 << 30, max_batch=6)
     srv.run(reqs)
     torch.cuda.synchronize()
     assert srv.batches > 3 and srv.max_inflight >= 2
+    assert all(torch.equal(K, K0) for K, K0 in zip(kernels, before))  # resident kernels only read
     for r in reqs:
         A = kernels[r.kernel].clone()
         alone = B.dpp_sample_ldlh(A, r.u, prec=prec)
