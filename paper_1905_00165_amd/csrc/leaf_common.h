@@ -25,13 +25,41 @@ namespace dpp {
 namespace leaf {
 
 constexpr int L = kLeaf;
-// Panel solves: 4 wavefronts per workgroup, each 4 groups of 16 panel rows
-// (or columns), so 256 per workgroup; a staged 16 x 64 tile per wavefront.
+// Panel solves: 4 wavefronts per workgroup, each `gpw` groups of 16 panel rows
+// (or columns), gpw = 1..kGroups; a staged 16 x 64 tile per wavefront.
 constexpr int kWaves = 4;
 constexpr int kGroups = 4;
-constexpr int kRows = kWaves * kGroups * 16;
 constexpr int kThreads = kWaves * 64;
 constexpr int kTilePitch = 66;  // doubles per row of a staged 16 x 64 tile
+
+// Every workgroup of a diagonal-block launch first runs the 64-step chain,
+// then its share of the panel, one group of 16 rows after the other on each
+// wavefront. The launch takes as long as one chain plus one workgroup's
+// groups, as long as all workgroups are resident at once: so give each
+// wavefront the fewest groups that keep the grid within one resident round
+// (`per_cu` workgroups on each of the device's compute units), at most
+// kGroups. Returns the groups per wavefront; *gx receives the grid width.
+inline int groups_per_wave(int64_t rows, int nprob, int per_cu, int* gx)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    const int64_t resident = (int64_t)cus * per_cu;
+    int g = 1;
+    for (; g < kGroups; ++g) {
+        const int64_t w = (rows + kWaves * 16 * g - 1) / (kWaves * 16 * g);
+        if (w * nprob <= resident) break;
+    }
+    const int64_t w = rows > 0 ? (rows + kWaves * 16 * g - 1) / (kWaves * 16 * g) : 1;
+    *gx = (int)w;
+    return g;
+}
 
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {

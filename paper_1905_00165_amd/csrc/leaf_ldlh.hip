@@ -27,13 +27,13 @@ using namespace leaf;
 // Then L21 = W D1^{-1}; A receives L21, the split planes W and L21.
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restrict__ probs, int64_t c0,
-                                               int64_t j0, int ss)
+                                               int64_t j0, int ss, int gpw)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
     if (c0 >= n) return;
     const int bs = (int)((n - c0) < L ? (n - c0) : L);
-    const int64_t row0 = c0 + bs + (int64_t)blockIdx.x * kRows;
+    const int64_t row0 = c0 + bs + (int64_t)blockIdx.x * (kWaves * 16 * gpw);
     if (blockIdx.x > 0 && row0 >= n) return;
 
     T* __restrict__ A = static_cast<T*>(P.A);
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
 
     const int lane = tid & 63;
     const int q = lane >> 4, i16 = lane & 15;
-    const int64_t wrow0 = row0 + (int64_t)(tid >> 6) * (kGroups * 16);
+    const int64_t wrow0 = row0 + (int64_t)(tid >> 6) * (16 * gpw);
     if (wrow0 >= n) return;
 
     // Strip = columns [c0, c0+64) from row wrow0 on, read from S and written
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
         strip_rsrc(S + wrow0 + c0 * lds, (int64_t)L * lds * (int64_t)sizeof(T));
     const int cstride = (int)(lda * (int64_t)sizeof(T));
     const int istride = (int)(lds * (int64_t)sizeof(T));
-    const int ngroups = (int)((n - wrow0 + 15) / 16) < kGroups ? (int)((n - wrow0 + 15) / 16) : kGroups;
+    const int ngroups = (int)((n - wrow0 + 15) / 16) < gpw ? (int)((n - wrow0 + 15) / 16) : gpw;
 
     auto row_of = [&](int g) {
         const int64_t r = wrow0 + 16 * g + i16;
@@ -220,11 +220,11 @@ template <typename T>
 hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, int64_t c0,
                     int64_t j0, int ss, hipStream_t s)
 {
-    const int64_t below = nmax - c0 - L;
-    const int gx = below > 0 ? (int)((below + kRows - 1) / kRows) : 1;
+    int gx = 1;
+    const int gpw = groups_per_wave(nmax - c0 - L, nprob, 2, &gx);  // two workgroups per CU
     dim3 grid(gx, nprob), block(kThreads);
-    if (split) hipLaunchKernelGGL((leaf_ldlh<T, true>), grid, block, 0, s, probs, c0, j0, ss);
-    else hipLaunchKernelGGL((leaf_ldlh<T, false>), grid, block, 0, s, probs, c0, j0, ss);
+    if (split) hipLaunchKernelGGL((leaf_ldlh<T, true>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    else hipLaunchKernelGGL((leaf_ldlh<T, false>), grid, block, 0, s, probs, c0, j0, ss, gpw);
     return hipGetLastError();
 }
 

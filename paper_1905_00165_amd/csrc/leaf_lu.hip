@@ -26,13 +26,13 @@ using namespace leaf;
 // chain, repeated per workgroup, dominates).
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
-                                             int64_t j0, int ss)
+                                             int64_t j0, int ss, int gpw)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
     if (c0 >= n) return;
     const int bs = (int)((n - c0) < L ? (n - c0) : L);
-    const int64_t idx0 = c0 + bs + (int64_t)blockIdx.x * kRows;
+    const int64_t idx0 = c0 + bs + (int64_t)blockIdx.x * (kWaves * 16 * gpw);
     if (blockIdx.x > 0 && idx0 >= n) return;
 
     T* __restrict__ A = static_cast<T*>(P.A);
@@ -136,9 +136,9 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
 
     const int lane = tid & 63;
     const int q = lane >> 4, i16 = lane & 15;
-    const int64_t w0 = idx0 + (int64_t)(tid >> 6) * (kGroups * 16);
+    const int64_t w0 = idx0 + (int64_t)(tid >> 6) * (16 * gpw);
     if (w0 >= n) return;
-    const int ngroups = (int)((n - w0 + 15) / 16) < kGroups ? (int)((n - w0 + 15) / 16) : kGroups;
+    const int ngroups = (int)((n - w0 + 15) / 16) < gpw ? (int)((n - w0 + 15) / 16) : gpw;
     double* const tile = sT + (tid >> 6) * (16 * kTilePitch);
     const int cstride = (int)(lda * (int64_t)sizeof(T));
     const int istride = (int)(lds * (int64_t)sizeof(T));
@@ -255,11 +255,11 @@ template <typename T>
 hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, int64_t c0,
                     int64_t j0, int ss, hipStream_t s)
 {
-    const int64_t below = nmax - c0 - L;
-    const int gx = below > 0 ? (int)((below + kRows - 1) / kRows) : 1;
+    int gx = 1;
+    const int gpw = groups_per_wave(nmax - c0 - L, nprob, 1, &gx);  // one workgroup per CU (LDS)
     dim3 grid(gx, nprob), block(kThreads);
-    if (split) hipLaunchKernelGGL((leaf_lu<T, true>), grid, block, 0, s, probs, c0, j0, ss);
-    else hipLaunchKernelGGL((leaf_lu<T, false>), grid, block, 0, s, probs, c0, j0, ss);
+    if (split) hipLaunchKernelGGL((leaf_lu<T, true>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    else hipLaunchKernelGGL((leaf_lu<T, false>), grid, block, 0, s, probs, c0, j0, ss, gpw);
     return hipGetLastError();
 }
 
