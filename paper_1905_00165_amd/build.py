@@ -4,6 +4,7 @@ next to this file (in-tree, so it travels with the source tree).
 import concurrent.futures as cf
 import glob
 import os
+import re
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,18 +26,44 @@ FLAGS = [
 ]
 
 
+def _spills(remarks):
+    """(kernel, VGPRs spilled) for every kernel of a file whose register
+    allocation spilled vector registers to scratch memory, from the compiler's
+    resource-usage remarks."""
+    out, name = [], None
+    for line in remarks:
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"VGPRs Spill: (\d+)", line)
+        if m and int(m.group(1)) > 0:
+            out.append((name, int(m.group(1))))
+    return out
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-fno-caret-diagnostics", "-c", src,
+           "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
+    lines = r.stderr.splitlines()
+    remarks = [l for l in lines if "kernel-resource-usage" in l]
     # hipcc's host pass warns that it does not know the packed-fp32 feature.
-    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    err = "\n".join(l for l in lines if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{err}")
     if err.strip() and verbose:
         print(err, flush=True)
+    # Every kernel here is written to fit its registers; a spill to scratch is
+    # a performance regression (the chain and the MFMA loops slow down several
+    # times), so it fails the build.
+    bad = _spills(remarks)
+    if bad:
+        raise RuntimeError(f"{os.path.basename(src)}: vector registers spilled to scratch in "
+                           + ", ".join(f"{k} ({n})" for k, n in bad))
     return obj
 
 

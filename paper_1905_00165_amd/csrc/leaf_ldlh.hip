@@ -44,9 +44,9 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
     // One LDS array carved by hand so that sB sits at address 0: the chain's
     // 64-entry broadcast reads then all use one base register and immediate
     // offsets.
-    __shared__ double smem[2 * L + L * L + 4 * 16 * 16 + kWaves * 16 * kTilePitch];
-    double* const sB = smem;               // broadcast column of the current pivot
-    double* const sR = smem + L;           // 1 / D1
+    __shared__ __attribute__((aligned(16))) double smem[2 * L + L * L + 4 * 16 * 16 + kWaves * 16 * kTilePitch];
+    double* const sB = smem;               // chain: broadcast columns of the current two pivots
+    double* const sR = smem + L;           // 1 / D1 (written after the chain, over sB's second half)
     double* const sL = smem + 2 * L;       // sL[t*L + k] = L11[k][t] for k > t, zero elsewhere
     double* const sI = sL + L * L;         // sI[b*256 + i*16 + k] = (L_bb^{-1})[i][k]
     double* const sT = sI + 4 * 16 * 16;   // per wavefront: W of one row group, row-major
@@ -75,9 +75,18 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
         int mykeep = 0;
         int me = lane;
 
+        // Two pivots per step: pivot j is decided, column j + 1 alone takes
+        // its rank-1 update from pivot j, pivot j + 1 is decided, and the
+        // columns after it take both rank-1 updates in the same order as two
+        // one-pivot steps would (so every value is the same, bit for bit). The
+        // two broadcast columns sit side by side in LDS, one 16-byte read per
+        // entry. Past a ragged block's end (j + 1 >= bs) column j + 1 is all
+        // zeros and u = 2 there, so that pivot rejects, l1 = -0 and its update
+        // adds zeros.
+        double2* const sB2 = reinterpret_cast<double2*>(sB);
 #pragma unroll
-        for (int j = 0; j < L; ++j) {
-            // Keeps the compiler from hoisting the 64 per-step lane masks
+        for (int j = 0; j < L; j += 2) {
+            // Keeps the compiler from hoisting the per-step lane masks
             // (lane == j, lane > j) out of the unrolled loop, where they
             // would occupy 128 scalar registers and spill.
             asm volatile("" : "+v"(me));
@@ -87,17 +96,35 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
                 const bool keep = uj < d;                // Bernoulli(d) with stream u_j
                 const double dp = keep ? d : d - 1.0;   // Prop. 4 on rejection
                 const double c = a[j];                   // A[lane][j], unscaled
-                sB[lane] = c;
-                __builtin_amdgcn_wave_barrier();
                 const double l = c / dp;
+                a[j + 1] -= l * readlane_d(c, j + 1);    // A[lane][j+1] -= l_lane * A[j+1][j]
+                const double d1 = readlane_d(a[j + 1], j + 1);
+                const double u1 = readlane_d(ul, j + 1);
+                const bool keep1 = u1 < d1;
+                const double dp1 = keep1 ? d1 : d1 - 1.0;
+                const double c1 = a[j + 1];
+                const double l1 = c1 / dp1;
+                sB2[lane] = make_double2(c, c1);
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
                 for (int k = 0; k < L; ++k)
-                    if (k > j) a[k] -= l * sB[k];  // A[lane][k] -= l_lane * A[k][j]
+                    if (k > j + 1) {
+                        const double2 v = sB2[k];  // A[k][j], A[k][j+1]
+                        a[k] -= l * v.x;
+                        a[k] -= l1 * v.y;
+                    }
+                // No LDS access moves across this point: hoisting the next
+                // step's reads would hold them in registers and spill.
+                asm volatile("" ::: "memory");
                 __builtin_amdgcn_wave_barrier();
                 const bool isj = me == j;
                 a[j] = isj ? dp : (me > j ? l : c);
                 mydp = isj ? dp : mydp;
                 mykeep = isj ? (keep ? 1 : 0) : mykeep;
+                const bool isj1 = me == j + 1;
+                a[j + 1] = isj1 ? dp1 : (me > j + 1 ? l1 : c1);
+                mydp = isj1 ? dp1 : mydp;
+                mykeep = isj1 ? (keep1 ? 1 : 0) : mykeep;
             }
         }
 
