@@ -55,6 +55,10 @@ def parse():
                         "one per stream (forked and joined inside the step)")
     p.add_argument("--no-graph", action="store_true",
                    help="launch every step eagerly instead of replaying a captured HIP graph")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="before the steps, copy K's lower triangle once with dpp_copy_lower "
+                        "(n(n+1)/2 entries read and written): a launch of known size against "
+                        "which hardware byte counters of a profiled run can be scaled")
     p.add_argument("--extra", type=int, default=1,
                    help="also measure the other workloads (n=1024 single sample, LU n=8192, "
                         "batched L-ensembles); 0 skips them")
@@ -78,6 +82,11 @@ def run_path(torch, B, K, us, prec, args, As, ws):
              "info": torch.empty(1, dtype=torch.int32, device=dev)} for _ in As]
 
     Kc = K.t()  # column-major view (K is symmetric)
+    if args.copy_probe:
+        scratch = torch.empty_like(K)
+        B.dpp_copy_lower(scratch.t(), Kc)
+        torch.cuda.synchronize()
+        del scratch
     S = max(1, min(args.streams, len(As)))
     groups = [list(range(g, len(As), S)) for g in range(S)]
     streams = [torch.cuda.Stream() for _ in range(S)] if S > 1 else []
