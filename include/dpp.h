@@ -122,7 +122,16 @@ size_t dpp_workspace_size(int hermitian, dpp_dtype dt, int64_t n, dpp_precision 
              (bit for bit), except that for LDL^H the strict upper triangle of
              A is not written. Each entry of K is read once, so no working copy
              of K is needed per sample. Several problems may share one K; no
-             problem's A may overlap another problem's A or K. */
+             problem's A may overlap another problem's A or K.
+     npiv    indices to decide (optional; 0 means n). 0 < npiv < n must be a
+             multiple of 64: only indices [0, npiv) are decided (mask, pivots,
+             loglik and info cover them; loglik is then the log-probability of
+             those decisions), and on exit the trailing block A[npiv:n, npiv:n]
+             (its lower triangle for LDL^H) holds the marginal kernel of the
+             remaining indices conditioned on those decisions: the Schur
+             complement of K - 1_{Y^c} restricted to the decided indices
+             (Props. 3-5). Sampling that block with its own call continues the
+             same chain. Argument error otherwise. */
 typedef struct {
     void* A;
     int64_t n;
@@ -134,6 +143,7 @@ typedef struct {
     int32_t* info;
     const void* K;
     int64_t ldk;
+    int64_t npiv;
 } dpp_problem;
 
 /*
@@ -174,6 +184,48 @@ dpp_status dpp_copy_lower(void* dst, const void* src, dpp_dtype dt, int64_t n, i
                           int64_t ld_src, void* stream);
 
 /* Static, NUL-terminated description of a status code. */
+/*
+ * dpp_lensemble_to_marginal_batched - on-device conversion of `count`
+ * Hermitian (real symmetric) L-ensemble kernels into marginal kernels,
+ * K = I - (L + I)^{-1}, the conversion the paper's closing section names as
+ * the natural companion of the blocked sampler, run on the sampler's own
+ * blocked LDL^H: the 2n' x 2n' matrix [[L + I, I], [I, 0]] (n' = n rounded up
+ * to 64, L padded with zeros) is factored through its first n' pivots with
+ * every pivot kept, which leaves -(L + I)^{-1} as the trailing Schur
+ * complement. FP64 arithmetic throughout.
+ *   probs  HOST array of `count` descriptors, read before the call returns:
+ *     L, n, ldl   in, n x n, storage type dt, column-major; only the lower
+ *                 triangle is read. L must be positive semi-definite.
+ *     K, ldk      out, n x n, storage type dt: the symmetric marginal kernel,
+ *                 both triangles written. K may be L itself (ldk == ldl);
+ *                 otherwise the two must not overlap.
+ *     logdet      out, optional (NULL): ln det(L + I), the log normalization
+ *                 constant of the L-ensemble.
+ *     info        out, int32: 0, or 1 if a pivot of L + I was not positive (L
+ *                 not positive semi-definite to working precision); K is then
+ *                 unspecified.
+ *   ws     device workspace of dpp_lensemble_workspace_size(ns, count) bytes
+ *          (about 32 n'^2 bytes per problem plus the factorization's).
+ * Argument errors (n < 1, bad leading dimensions, 2n' > 2^20, NULL pointers,
+ * overlapping L and K) return synchronously before any launch.
+ */
+typedef struct {
+    const void* L;
+    int64_t n;
+    int64_t ldl;
+    void* K;
+    int64_t ldk;
+    double* logdet;
+    int32_t* info;
+} dpp_lensemble;
+
+dpp_status dpp_lensemble_to_marginal_batched(const dpp_lensemble* probs, int64_t count,
+                                             dpp_dtype dt, void* ws, size_t ws_bytes,
+                                             void* stream);
+/* Workspace bytes for conversions of sizes ns[0..count-1] (host array); 0 for
+   invalid arguments. */
+size_t dpp_lensemble_workspace_size(const int64_t* ns, int64_t count);
+
 const char* dpp_status_string(dpp_status s);
 
 /*

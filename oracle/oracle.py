@@ -99,6 +99,27 @@ def conditional_pivot(K, mask_prefix, j):
     return float(K[j, j] - K[j, :j] @ x)
 
 
+def conditional_kernel(K, mask_prefix):
+    """Marginal kernel of the indices m.. given the decisions mask_prefix on
+    0..m-1 (Props. 3-5): the Schur complement of K_A - 1_{A excluded} in K,
+    A = [0, m),
+        K_BB - K_BA (K_A - diag(1 - mask_A))^{-1} K_AB,   B = [m, n).
+    Uses a library solve; cost O(n^3)."""
+    K = np.asarray(K, dtype=np.float64)
+    m = len(mask_prefix)
+    if m == 0:
+        return K.copy()
+    KA = K[:m, :m] - np.diag(1.0 - np.asarray(mask_prefix, dtype=np.float64))
+    return K[m:, m:] - K[m:, :m] @ np.linalg.solve(KA, K[:m, m:])
+
+
+def lensemble_marginal(L):
+    """Marginal kernel of the L-ensemble with kernel L: K = I - (L + I)^{-1}
+    (equivalently L (L + I)^{-1}), by a library inverse."""
+    L = np.asarray(L, dtype=np.float64)
+    return np.eye(L.shape[0]) - np.linalg.inv(L + np.eye(L.shape[0]))
+
+
 def reconstruct_ldlh(A):
     """L D L^T from a factored lower triangle (strict lower = L, diagonal = D)."""
     A = np.asarray(A, dtype=np.float64)

@@ -31,7 +31,13 @@ class DppError(RuntimeError):
 
 class dpp_problem(ctypes.Structure):
     _fields_ = [("A", _vp), ("n", _i64), ("lda", _i64), ("u", _vp), ("mask", _vp),
-                ("pivots", _vp), ("loglik", _vp), ("info", _vp), ("K", _vp), ("ldk", _i64)]
+                ("pivots", _vp), ("loglik", _vp), ("info", _vp), ("K", _vp), ("ldk", _i64),
+                ("npiv", _i64)]
+
+
+class dpp_lensemble(ctypes.Structure):
+    _fields_ = [("L", _vp), ("n", _i64), ("ldl", _i64), ("K", _vp), ("ldk", _i64),
+                ("logdet", _vp), ("info", _vp)]
 
 
 class dpp_kernel_stats(ctypes.Structure):
@@ -67,6 +73,11 @@ def lib() -> ctypes.CDLL:
     L.dpp_workspace_size_batched.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64),
                                              _i64, ctypes.c_int]
     L.dpp_workspace_size_batched.restype = ctypes.c_size_t
+    L.dpp_lensemble_to_marginal_batched.argtypes = [ctypes.POINTER(dpp_lensemble), _i64,
+                                                    ctypes.c_int, _vp, ctypes.c_size_t, _vp]
+    L.dpp_lensemble_to_marginal_batched.restype = ctypes.c_int
+    L.dpp_lensemble_workspace_size.argtypes = [ctypes.POINTER(_i64), _i64]
+    L.dpp_lensemble_workspace_size.restype = ctypes.c_size_t
     L.dpp_copy_lower.argtypes = [_vp, _vp, ctypes.c_int, _i64, _i64, _i64, _vp]
     L.dpp_copy_lower.restype = ctypes.c_int
     L.dpp_status_string.argtypes = [ctypes.c_int]
@@ -210,12 +221,14 @@ def dpp_sample_lu(A, u, prec=DPP_PREC_FP64, ws=None, out=None):
     return _single("dpp_sample_lu", False, A, u, prec, ws, out)
 
 
-def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None):
+def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None, npivs=None):
     torch = _torch()
     if len(As) != len(us) or not As:
         raise ValueError("need matching, non-empty lists of matrices and streams")
     if Ks is not None and len(Ks) != len(As):
         raise ValueError("Ks needs one source matrix (or None) per problem")
+    if npivs is not None and len(npivs) != len(As):
+        raise ValueError("npivs needs one count (or 0 for all) per problem")
     dt = _dtype_code(As[0])
     probs = (dpp_problem * len(As))()
     res = []
@@ -236,7 +249,7 @@ def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None):
         o = _outputs(n, A.device, outs[i] if outs else None)
         probs[i] = dpp_problem(A.data_ptr(), n, lda, u.data_ptr(), o["mask"].data_ptr(),
                                o["pivots"].data_ptr(), o["loglik"].data_ptr(),
-                               o["info"].data_ptr(), kp, ldk)
+                               o["info"].data_ptr(), kp, ldk, int(npivs[i]) if npivs else 0)
         res.append(o)
         ns.append(n)
     need = dpp_workspace_size_batched(hermitian, dt, ns, prec)
@@ -249,14 +262,57 @@ def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None):
     return res
 
 
-def dpp_sample_ldlh_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=None):
+def dpp_sample_ldlh_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=None, npivs=None):
     """Independent symmetric problems in one launch sequence. With Ks (one
     column-major source per problem, or None for in place), each K is read
-    only and its A receives the factor (lower triangle)."""
-    return _batched("dpp_sample_ldlh_batched", True, As, us, prec, ws, outs, Ks)
+    only and its A receives the factor (lower triangle). With npivs (0 = all),
+    problem i decides only its first npivs[i] indices (a multiple of 64) and
+    leaves the conditional marginal kernel of the rest in A's trailing block."""
+    return _batched("dpp_sample_ldlh_batched", True, As, us, prec, ws, outs, Ks, npivs)
 
 
-def dpp_sample_lu_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=None):
-    """Independent general problems in one launch sequence; Ks as for
+def dpp_sample_lu_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=None, npivs=None):
+    """Independent general problems in one launch sequence; Ks and npivs as for
     dpp_sample_ldlh_batched."""
-    return _batched("dpp_sample_lu_batched", False, As, us, prec, ws, outs, Ks)
+    return _batched("dpp_sample_lu_batched", False, As, us, prec, ws, outs, Ks, npivs)
+
+
+def dpp_lensemble_workspace_size(ns) -> int:
+    arr = (_i64 * len(ns))(*[int(n) for n in ns])
+    return int(lib().dpp_lensemble_workspace_size(arr, len(ns)))
+
+
+def dpp_lensemble_to_marginal_batched(Ls, Ks=None, ws=None):
+    """K_i = I - (L_i + I)^{-1} for symmetric positive semi-definite L_i
+    (column-major device tensors, lower triangle read), on the device. Ks: one
+    output per problem (None: allocated; it may be L_i itself). Returns a list
+    of dicts with K, logdet (ln det(L + I), 1-element FP64 tensor) and info."""
+    torch = _torch()
+    if not Ls:
+        raise ValueError("need a non-empty list of matrices")
+    dt = _dtype_code(Ls[0])
+    probs = (dpp_lensemble * len(Ls))()
+    res = []
+    for i, Lm in enumerate(Ls):
+        n, ldl = _check_matrix(Lm)
+        if _dtype_code(Lm) != dt:
+            raise ValueError("all matrices of a batch share one dtype")
+        K = Ks[i] if Ks is not None and Ks[i] is not None else torch.empty_like(Lm)
+        nk, ldk = _check_matrix(K)
+        if nk != n or _dtype_code(K) != dt:
+            raise ValueError("each K must match its L in size and dtype")
+        o = {"K": K, "logdet": torch.empty(1, dtype=torch.float64, device=Lm.device),
+             "info": torch.empty(1, dtype=torch.int32, device=Lm.device)}
+        probs[i] = dpp_lensemble(Lm.data_ptr(), n, ldl, K.data_ptr(), ldk,
+                                 o["logdet"].data_ptr(), o["info"].data_ptr())
+        res.append(o)
+    need = dpp_lensemble_workspace_size([Lm.shape[0] for Lm in Ls])
+    if need == 0:
+        raise ValueError("sizes out of range for the conversion")
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=Ls[0].device)
+    st = lib().dpp_lensemble_to_marginal_batched(probs, len(Ls), dt, ws.data_ptr(), ws.numel(),
+                                                 _stream_handle(Ls[0].device))
+    if st != DPP_OK:
+        raise DppError(st, "dpp_lensemble_to_marginal_batched")
+    return res

@@ -155,6 +155,7 @@ struct Ctx {
     const DevProb* probs;  // device
     int count;
     int64_t nmax;
+    int64_t pmax;          // largest npiv: no diagonal block at or past it is decided
     hipStream_t s;
     const std::vector<int64_t>* ns;  // host copy of the problem sizes
     bool profiling;
@@ -253,7 +254,7 @@ dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
 // bit-identical results) alone and in any batch.
 dpp_status factor_panel(const Ctx& c, int64_t c0, int64_t w, int64_t j0)
 {
-    if (c0 >= c.nmax) return DPP_OK;
+    if (c0 >= c.pmax) return DPP_OK;
     if (w <= kLeaf) return leaf(c, c0, j0);
     const int64_t h = w / 2, mid = c0 + h;
     dpp_status st = factor_panel(c, c0, h, j0);
@@ -273,7 +274,7 @@ dpp_status lu_panel(const Ctx& c, int64_t j0)
 {
     const int64_t j1 = j0 + c.plan.B0;
     constexpr int64_t kAll = (int64_t)1 << 62;
-    for (int64_t c0 = j0; c0 < j1 && c0 < c.nmax; c0 += kLeaf) {
+    for (int64_t c0 = j0; c0 < j1 && c0 < c.pmax; c0 += kLeaf) {
         dpp_status st = leaf(c, c0, j0);
         if (st != DPP_OK) return st;
         const int64_t x = c0 + kLeaf;
@@ -295,7 +296,7 @@ int64_t size_group(int64_t n) { return n <= 2048 ? (n + 127) / 128 : 16 + (n + 1
 dpp_status run_group(const Ctx& c)
 {
     const Plan& plan = c.plan;
-    for (int64_t j0 = 0; j0 < c.nmax; j0 += plan.B0) {
+    for (int64_t j0 = 0; j0 < c.pmax; j0 += plan.B0) {
         const int64_t j1 = j0 + plan.B0;
         dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : lu_panel(c, j0);
         if (st != DPP_OK) return st;
@@ -335,6 +336,8 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
             !q.loglik || !q.info)
             return DPP_ERR_INVALID_ARG;
         if (q.K && !source_ok(q, dt)) return DPP_ERR_INVALID_ARG;
+        if (q.npiv < 0 || q.npiv > q.n || (q.npiv % dpp::kLeaf != 0 && q.npiv != q.n))
+            return DPP_ERR_INVALID_ARG;
         nmax = q.n > nmax ? q.n : nmax;
     }
     const Plan plan = make_plan(herm, dt, prec, nmax);
@@ -370,6 +373,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.lda = q.lda;
         d.K = q.K ? q.K : q.A;
         d.ldk = q.K ? q.ldk : q.lda;
+        d.npiv = q.npiv ? q.npiv : q.n;
         d.u = q.u;
         d.mask = q.mask;
         d.piv = q.pivots;
@@ -387,7 +391,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     }
     std::vector<int64_t> ns_all((size_t)count);
     for (int64_t p = 0; p < count; ++p) ns_all[(size_t)p] = host[(size_t)p].n;
-    Ctx c{plan, static_cast<const DevProb*>(ws), (int)count, nmax, s, &ns_all, profiling};
+    Ctx c{plan, static_cast<const DevProb*>(ws), (int)count, nmax, nmax, s, &ns_all, profiling};
 
     // Descriptors reach the device as kernel arguments (copied at launch), so
     // the call neither reads host memory later nor blocks the host.
@@ -403,7 +407,10 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         int64_t p1 = p0 + 1;
         while (p1 < count && size_group(host[(size_t)p1].n) == size_group(host[(size_t)p0].n)) ++p1;
         std::vector<int64_t> ns(ns_all.begin() + p0, ns_all.begin() + p1);
-        const Ctx g{plan, c.probs + p0, (int)(p1 - p0), host[(size_t)(p1 - 1)].n, s, &ns, profiling};
+        int64_t pmax = 0;
+        for (int64_t p = p0; p < p1; ++p) pmax = std::max(pmax, host[(size_t)p].npiv);
+        const Ctx g{plan, c.probs + p0, (int)(p1 - p0), host[(size_t)(p1 - 1)].n, pmax, s, &ns,
+                    profiling};
         const dpp_status st = run_group(g);
         if (st != DPP_OK) return st;
         p0 = p1;
@@ -426,9 +433,130 @@ size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t cou
     return need;
 }
 
+// ------------------------------------------------- L-ensemble conversion
+int64_t lens_np(int64_t n) { return (n + kLeaf - 1) / kLeaf * kLeaf; }
+
+// Per-problem workspace of the conversion: the augmented matrix and the
+// factorization's inputs and outputs for it.
+size_t lens_problem_bytes(int64_t n)
+{
+    const size_t m = (size_t)(2 * lens_np(n));
+    return align_up(m * m * sizeof(double)) + 2 * align_up(m * sizeof(double)) + align_up(m) +
+           align_up(sizeof(double)) + align_up(sizeof(int32_t));
+}
+
+size_t lens_desc_bytes(int64_t count) { return align_up((size_t)count * sizeof(dpp::LensDesc)); }
+
+size_t lens_workspace(const int64_t* ns, int64_t count, std::vector<int64_t>* ms_out = nullptr)
+{
+    if (!ns || count < 1 || count > 65535) return 0;
+    std::vector<int64_t> ms((size_t)count);
+    size_t need = lens_desc_bytes(count);
+    for (int64_t i = 0; i < count; ++i) {
+        if (ns[i] < 1 || 2 * lens_np(ns[i]) > kMaxLda) return 0;
+        ms[(size_t)i] = 2 * lens_np(ns[i]);
+        need += lens_problem_bytes(ns[i]);
+    }
+    const size_t sw = workspace_batched(true, DPP_F64, ms.data(), count, DPP_PREC_FP64);
+    if (!sw) return 0;
+    if (ms_out) *ms_out = ms;
+    return need + sw;
+}
+
+// Input and output of one conversion: K may be L itself (same leading
+// dimension: L is consumed before K is written), else the two must not overlap.
+bool lens_args_ok(const dpp_lensemble& q, dpp_dtype dt)
+{
+    if (!q.L || !q.K || !q.info || q.n < 1 || q.ldl < q.n || q.ldk < q.n || q.ldl > kMaxLda ||
+        q.ldk > kMaxLda)
+        return false;
+    if (q.K == q.L) return q.ldk == q.ldl;
+    const uintptr_t elt = dt == DPP_F64 ? 8 : 4;
+    const uintptr_t l0 = reinterpret_cast<uintptr_t>(q.L), k0 = reinterpret_cast<uintptr_t>(q.K);
+    const uintptr_t l1 = l0 + (uintptr_t)((q.n - 1) * q.ldl + q.n) * elt;
+    const uintptr_t k1 = k0 + (uintptr_t)((q.n - 1) * q.ldk + q.n) * elt;
+    return l1 <= k0 || k1 <= l0;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t dpp_lensemble_workspace_size(const int64_t* ns, int64_t count)
+{
+    return lens_workspace(ns, count);
+}
+
+dpp_status dpp_lensemble_to_marginal_batched(const dpp_lensemble* probs, int64_t count,
+                                             dpp_dtype dt, void* ws, size_t ws_bytes,
+                                             void* stream)
+{
+    if (!probs || count < 1 || count > 65535 || (dt != DPP_F64 && dt != DPP_F32))
+        return DPP_ERR_INVALID_ARG;
+    std::vector<int64_t> ns((size_t)count);
+    int64_t nmax = 0, mmax = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        if (!lens_args_ok(probs[i], dt)) return DPP_ERR_INVALID_ARG;
+        ns[(size_t)i] = probs[i].n;
+        nmax = std::max(nmax, probs[i].n);
+    }
+    std::vector<int64_t> ms;
+    const size_t need = lens_workspace(ns.data(), count, &ms);
+    if (need == 0) return DPP_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < need) return DPP_ERR_WORKSPACE;
+    const dpp_status dev = device_ok();
+    if (dev != DPP_OK) return dev;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int dcode = dt == DPP_F64 ? 0 : 1;
+
+    // Workspace: descriptors, then per problem the augmented matrix, u,
+    // pivots, mask, loglik and info, then the factorization's own workspace.
+    char* cursor = static_cast<char*>(ws) + lens_desc_bytes(count);
+    std::vector<dpp::LensDesc> host((size_t)count);
+    std::vector<dpp_problem> fact((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        const dpp_lensemble& q = probs[i];
+        const int64_t m = ms[(size_t)i];
+        dpp::LensDesc& d = host[(size_t)i];
+        d.L = q.L;
+        d.K = q.K;
+        d.n = q.n;
+        d.ldl = q.ldl;
+        d.ldk = q.ldk;
+        d.np = m / 2;
+        d.aug = reinterpret_cast<double*>(cursor);
+        cursor += align_up((size_t)(m * m) * sizeof(double));
+        d.u = reinterpret_cast<double*>(cursor);
+        cursor += align_up((size_t)m * sizeof(double));
+        double* piv = reinterpret_cast<double*>(cursor);
+        cursor += align_up((size_t)m * sizeof(double));
+        d.mask = reinterpret_cast<uint8_t*>(cursor);
+        cursor += align_up((size_t)m);
+        d.loglik = reinterpret_cast<double*>(cursor);
+        cursor += align_up(sizeof(double));
+        d.sinfo = reinterpret_cast<int32_t*>(cursor);
+        cursor += align_up(sizeof(int32_t));
+        d.logdet = q.logdet;
+        d.info = q.info;
+        mmax = std::max(mmax, m);
+        fact[(size_t)i] = dpp_problem{d.aug, m, m, d.u, d.mask, piv, d.loglik, d.sinfo,
+                                      nullptr, 0, d.np};
+    }
+    dpp::LensDesc* ddesc = static_cast<dpp::LensDesc*>(ws);
+    for (int64_t i = 0; i < count; i += dpp::kLensDescPerLaunch) {
+        const int cnt = (int)std::min<int64_t>(count - i, dpp::kLensDescPerLaunch);
+        if (dpp::launch_store_lens_descs(host.data() + i, cnt, ddesc + i, s) != hipSuccess)
+            return DPP_ERR_HIP;
+    }
+    if (dpp::launch_lens_augment(dcode, ddesc, (int)count, mmax, s) != hipSuccess) return DPP_ERR_HIP;
+    const size_t rest = ws_bytes - (size_t)(cursor - static_cast<char*>(ws));
+    const dpp_status st =
+        run(true, fact.data(), count, DPP_F64, DPP_PREC_FP64, cursor, rest, stream);
+    if (st != DPP_OK) return st;
+    if (dpp::launch_lens_extract(dcode, ddesc, (int)count, nmax, s) != hipSuccess) return DPP_ERR_HIP;
+    if (dpp::launch_lens_status(ddesc, (int)count, s) != hipSuccess) return DPP_ERR_HIP;
+    return DPP_OK;
+}
 
 dpp_status dpp_copy_lower(void* dst, const void* src, dpp_dtype dt, int64_t n, int64_t ld_dst,
                           int64_t ld_src, void* stream)

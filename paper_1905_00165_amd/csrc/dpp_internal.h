@@ -18,6 +18,7 @@ struct DevProb {
     int64_t lda;
     const void* K;    // the kernel, leading dimension ldk: read where an entry is
     int64_t ldk;      // read first (first_source below); K == A in place
+    int64_t npiv;     // indices decided: [0, npiv), npiv = n or a multiple of 64
     const double* u;  // n uniforms
     uint8_t* mask;    // n
     double* piv;      // n, pivots after the decision
@@ -111,5 +112,27 @@ hipError_t launch_store_diag(bool herm, int dtype, const DevProb* probs, int npr
 // argument block of a one-workgroup launch.
 constexpr int kDescPerLaunch = 36;  // 36 descriptors + count fit the 4 KiB argument block
 hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStream_t s);
+
+// L-ensemble conversion (lensemble.hip): one problem's device descriptor.
+struct LensDesc {
+    const void* L;     // n x n, ldl, storage type T (lower triangle read)
+    void* K;           // n x n, ldk, storage type T (written in full)
+    int64_t n, ldl, ldk;
+    int64_t np;        // n rounded up to a multiple of 64; the augmented matrix is 2np x 2np
+    double* aug;       // 2np x 2np FP64, column-major, leading dimension 2np
+    double* u;         // 2np zeros (every pivot kept)
+    uint8_t* mask;     // 2np, from the factorization of the first np pivots
+    double* loglik;    // 1: sum of the logs of the first np pivots
+    int32_t* sinfo;    // 1: the factorization's info word
+    double* logdet;    // 1 or nullptr: ln det(L + I)
+    int32_t* info;     // 1: 0, or 1 if L + I is not numerically positive definite
+};
+constexpr int kLensDescPerLaunch = 36;  // 36 descriptors + count fit the 4 KiB argument block
+hipError_t launch_store_lens_descs(const LensDesc* host, int cnt, LensDesc* dst, hipStream_t s);
+hipError_t launch_lens_augment(int dtype, const LensDesc* descs, int count, int64_t mmax,
+                               hipStream_t s);
+hipError_t launch_lens_extract(int dtype, const LensDesc* descs, int count, int64_t nmax,
+                               hipStream_t s);
+hipError_t launch_lens_status(const LensDesc* descs, int count, hipStream_t s);
 
 }  // namespace dpp

@@ -1,7 +1,8 @@
 // Log-likelihood and info word of each problem (gfx950).
 //
 // The likelihood of the returned sample is the product of the absolute values
-// of the modified pivots (Theorem 2), so loglik = sum_j ln|d'_j|. The sum runs
+// of the modified pivots (Theorem 2), so loglik = sum_j ln|d'_j| over the
+// decided indices j < npiv (the probability of those decisions). The sum runs
 // in a fixed order (each thread sums a contiguous chunk in index order, then a
 // fixed binary tree), so the result is bitwise reproducible. info is the
 // 1-based index of the first pivot that is exactly zero or NaN (0 if none).
@@ -15,7 +16,7 @@ constexpr int kThreads = 256;
 __global__ __launch_bounds__(kThreads) void finalize(const DevProb* __restrict__ probs)
 {
     const DevProb P = probs[blockIdx.x];
-    const int64_t n = P.n;
+    const int64_t n = P.npiv;  // the decided indices
     const int tid = threadIdx.x;
     const int64_t chunk = (n + kThreads - 1) / kThreads;
     const int64_t lo = tid * chunk;
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void store_diag(const DevProb* __restrict__ pr
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t c0 = (int64_t)blockIdx.x * kLeaf;
-    if (c0 >= P.n) return;
+    if (c0 >= P.npiv) return;  // blocks past npiv hold the conditional kernel, not factors
     const int bs = (int)((P.n - c0) < kLeaf ? (P.n - c0) : kLeaf);
     const double* blk = P.diag + (int64_t)blockIdx.x * kLeaf * kLeaf;
     T* A = static_cast<T*>(P.A);

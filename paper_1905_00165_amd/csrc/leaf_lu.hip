@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
-    if (c0 >= n) return;
+    if (c0 >= P.npiv) return;  // npiv <= n: only the first npiv indices are decided
     const int bs = (int)((n - c0) < L ? (n - c0) : L);
     const int64_t idx0 = c0 + bs + (int64_t)blockIdx.x * (kWaves * 16 * gpw);
     if (blockIdx.x > 0 && idx0 >= n) return;

@@ -186,7 +186,9 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
     const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
     const int64_t nrows = rEnd - rg.r0, ncols = cEnd - rg.c0;
-    if (nrows <= 0 || ncols <= 0 || k0 + kw > n) return;
+    if (nrows <= 0 || ncols <= 0 || k0 + kw > n || k0 >= P.npiv) return;
+    // Only decided columns contribute: k in [k0, min(k0 + kw, npiv)).
+    const int kwp = k0 + kw <= P.npiv ? kw : (int)(P.npiv - k0);
     const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (ncols + S::TN - 1) / S::TN;
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     };
 
     double cva[CP][16], cvb[CP][16];
-    const int nstages = kw / S::KC;
+    const int nstages = kwp / S::KC;
     for (int p = 0; p < S::NST - 1; ++p)
         if (p < nstages) issue_stage(p * S::KC, p);
     for (int st = 0; st < nstages; ++st) {

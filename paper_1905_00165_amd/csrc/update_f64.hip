@@ -68,7 +68,9 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
     const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
     const int64_t nrows = rEnd - rg.r0, ncols = cEnd - rg.c0;
-    if (nrows <= 0 || ncols <= 0 || k0 + kw > n) return;
+    if (nrows <= 0 || ncols <= 0 || k0 + kw > n || k0 >= P.npiv) return;
+    // Only decided columns contribute: k in [k0, min(k0 + kw, npiv)).
+    if (k0 + kw > P.npiv) kw = (int)(P.npiv - k0);
     const int64_t NR = (nrows + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
     // XCD-contiguous tile order (grid size is a multiple of 8).
     const int64_t per_xcd = gridDim.x / 8;

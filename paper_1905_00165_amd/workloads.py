@@ -121,6 +121,23 @@ def lensemble_kernel(n: int, seed: int, rank: int = 64, dtype=np.float32, out=No
     return out
 
 
+def lensemble_L(n: int, seed: int, rank: int = 64, dtype=np.float64, out=None):
+    """The L-ensemble kernel L = F F^T behind ``lensemble_kernel`` (same draws,
+    F = diag(q) Phi), formed in FP64 and stored in `dtype`; with ``out`` (a
+    column-major n x n torch tensor on a device) the product runs there."""
+    rng = np.random.default_rng(seed)
+    Phi = rng.normal(0.0, 1.0 / np.sqrt(rank), size=(n, rank))
+    q = rng.lognormal(0.0, 0.5, size=n)
+    F = q[:, None] * Phi
+    if out is None:
+        return np.asfortranarray(symmetrize_lower(F @ F.T).astype(dtype))
+    import torch
+    Fd = torch.from_numpy(F).to(out.device)
+    L = Fd @ Fd.T
+    out.copy_(torch.tril(L) + torch.tril(L, -1).T)
+    return out
+
+
 def lensemble_batch_sizes(count: int, seed: int, lo: int = 64, hi: int = 1024) -> np.ndarray:
     """n_i ~ U{lo..hi} (inclusive) for a batch of L-ensemble kernels."""
     return np.random.default_rng(seed).integers(lo, hi + 1, size=count)

@@ -124,6 +124,24 @@ def test_out_of_place_source_errors():
     assert call(p, n + 1) == 1                   # K == A with another leading dimension
 
 
+def test_partial_and_lensemble_argument_errors():
+    """npiv must be 0, n, or a multiple of 64 below n; an L-ensemble output may
+    not overlap its input unless it is the same buffer with the same leading
+    dimension; sizes whose augmented matrix exceeds 2^20 are refused."""
+    lib = B.lib()
+    p, n = 0x100000, 200
+    ws = ctypes.c_void_p(p)
+    for bad in (-64, 100, n + 64):
+        probs = (B.dpp_problem * 1)(B.dpp_problem(p, n, n, p, p, p, p, p, None, 0, bad))
+        assert lib.dpp_sample_ldlh_batched(probs, 1, 0, 0, ws, 1 << 40, None) == 1
+    q = (B.dpp_lensemble * 1)(B.dpp_lensemble(p, 10, 10, p + 8 * 40, 10, None, p))
+    assert lib.dpp_lensemble_to_marginal_batched(q, 1, 0, ws, 1 << 40, None) == 1
+    q = (B.dpp_lensemble * 1)(B.dpp_lensemble(p, 10, 10, p, 12, None, p))
+    assert lib.dpp_lensemble_to_marginal_batched(q, 1, 0, ws, 1 << 40, None) == 1
+    assert B.dpp_lensemble_workspace_size([(1 << 19) + 1]) == 0
+    assert B.dpp_lensemble_workspace_size([100]) > 32 * 128 * 128
+
+
 def test_profile_without_launches_is_empty():
     B.dpp_profile_begin()
     assert B.dpp_profile_end() == {}

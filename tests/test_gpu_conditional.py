@@ -1,0 +1,144 @@
+"""GPU checks of the partial factorization (decide the first npiv indices and
+leave the conditional marginal kernel of the rest, Props. 3-5) and of the
+on-device L-ensemble conversion K = I - (L + I)^{-1} built on it, against the
+oracle: its partial in-place run and its plain definitions (library solve and
+library inverse)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_00165_amd import workloads as W
+from parity import compare
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5)}
+PREC_ID = {0: "fp64", 1: "split"}
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_00165_amd import binding
+    return binding
+
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
+@pytest.mark.parametrize("prec", [0, 1], ids=lambda p: PREC_ID[p])
+def test_partial_run_leaves_the_conditional_kernel(B, herm, prec):
+    """Problems of one batch decide 256, 512 or all 700 of their indices (and
+    one of 1100 decides 576): the decided prefix matches the oracle's run on
+    the same stream and equals the full run's prefix bit for bit, and the
+    trailing block matches the oracle's partially factored matrix."""
+    tol, thr = TOL[prec]
+    cases = [(700, 256), (700, 512), (700, 0), (1100, 576)]
+    Ks = [W.hermitian_kernel(n, seed=80 + i) if herm else W.similarity_kernel(n, seed=80 + i)[0]
+          for i, (n, _) in enumerate(cases)]
+    us = [W.uniform_stream(n, seed=8000 + i) for i, (n, _) in enumerate(cases)]
+    As = [B.colmajor(K, device=DEV) for K in Ks]
+    uts = [torch.from_numpy(u).to(DEV) for u in us]
+    fb = B.dpp_sample_ldlh_batched if herm else B.dpp_sample_lu_batched
+    outs = fb(As, uts, prec=prec, npivs=[p for _, p in cases])
+    full = fb([B.colmajor(K, device=DEV) for K in Ks], uts, prec=prec)
+    torch.cuda.synchronize()
+    sampler = oracle.ldlh if herm else oracle.lu
+    for (n, p), K, u, A, o, f in zip(cases, Ks, us, As, outs, full):
+        m = p or n
+        mask, piv = o["mask"].cpu().numpy()[:m], o["pivots"].cpu().numpy()[:m]
+        assert np.array_equal(mask, f["mask"].cpu().numpy()[:m])
+        assert np.array_equal(piv, f["pivots"].cpu().numpy()[:m])
+        R = np.array(K, dtype=np.float64, order="F", copy=True)
+        ref = sampler(R, u, npiv=m, inplace=True)
+        pref = {"mask": ref["mask"][:m], "predec": ref["predec"][:m], "loglik": ref["loglik"]}
+        v = compare(mask, piv, float(o["loglik"].cpu()[0]), pref, u[:m], tol, thr)
+        assert int(o["info"].cpu()[0]) == 0
+        assert v.ok, v.why
+        if p and not v.near_tie:
+            S = A.cpu().numpy()[m:, m:]
+            S_ref = R[m:, m:]
+            if herm:
+                S, S_ref = np.tril(S), np.tril(S_ref)
+            err = float(np.max(np.abs(S - S_ref))) / max(1.0, float(np.max(np.abs(S_ref))))
+            print(f"[accuracy] {'ldlh' if herm else 'lu'} {PREC_ID[prec]} n={n} npiv={m} "
+                  f"max |S_gpu - S_oracle| / max(1, max |S|) = {err:.3e}")
+            assert err <= tol * 10
+
+
+def test_partial_argument_errors(B):
+    A = torch.zeros((200, 200), dtype=torch.float64, device=DEV).t()
+    u = torch.zeros(200, dtype=torch.float64, device=DEV)
+    for bad in (-64, 100, 256):
+        with pytest.raises(B.DppError):
+            B.dpp_sample_ldlh_batched([A], [u], npivs=[bad])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_lensemble_conversion_matches_the_inverse(B, dtype):
+    """K = I - (L + I)^{-1} on the device for L-ensembles of rank 64 and
+    several sizes (ragged against the 64-wide blocks), against a library
+    inverse of the same (storage-rounded) L; ln det(L + I) against a library
+    log-determinant; both triangles of K written."""
+    ns = [1, 5, 64, 100, 300, 700]
+    Lh = [W.lensemble_L(n, seed=900 + i) for i, n in enumerate(ns)]
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    Ls = [B.colmajor(L.astype(npdt), device=DEV, dtype=dtype) for L in Lh]
+    outs = B.dpp_lensemble_to_marginal_batched(Ls)
+    torch.cuda.synchronize()
+    tol = 1e-10 if dtype == torch.float64 else 2e-6
+    for n, L, o in zip(ns, Lh, outs):
+        Lr = L.astype(npdt).astype(np.float64)
+        K_ref = oracle.lensemble_marginal(Lr)
+        K = o["K"].cpu().numpy().astype(np.float64)
+        err = float(np.max(np.abs(K - K_ref)))
+        print(f"[accuracy] lensemble {dtype} n={n} max |K_gpu - K_ref| = {err:.3e}")
+        assert int(o["info"].cpu()[0]) == 0
+        assert err <= tol
+        sign, ld = np.linalg.slogdet(Lr + np.eye(n))
+        assert sign > 0
+        assert abs(float(o["logdet"].cpu()[0]) - ld) <= 1e-9 * max(1.0, abs(ld))
+
+
+def test_lensemble_conversion_in_place_and_then_sampled(B):
+    """K written over L (same buffer), then sampled: the sample equals the
+    oracle's on the library-inverse K (FP64 path, same stream)."""
+    n = 400
+    L = W.lensemble_L(n, seed=950)
+    buf = B.colmajor(L, device=DEV)
+    o = B.dpp_lensemble_to_marginal_batched([buf], Ks=[buf])[0]
+    assert o["K"].data_ptr() == buf.data_ptr()
+    u = W.uniform_stream(n, seed=951)
+    s = B.dpp_sample_ldlh(buf.clone(), torch.from_numpy(u).to(DEV), prec=0)
+    torch.cuda.synchronize()
+    K_ref = oracle.lensemble_marginal(L)
+    ref = oracle.ldlh(K_ref, u)
+    v = compare(s["mask"].cpu().numpy(), s["pivots"].cpu().numpy(), float(s["loglik"].cpu()[0]),
+                ref, u, 1e-9, 1e-10)
+    assert v.ok, v.why
+    assert int(s["mask"].sum().item()) <= 64
+
+
+def test_lensemble_conversion_flags_an_indefinite_l(B):
+    """L with an eigenvalue below -1 makes L + I indefinite: info = 1."""
+    n = 130
+    rng = np.random.default_rng(960)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.random(n)
+    lam[50] = -3.0
+    L = W.symmetrize_lower((Q * lam) @ Q.T)
+    good = W.lensemble_L(n, seed=961)
+    outs = B.dpp_lensemble_to_marginal_batched([B.colmajor(L, device=DEV), B.colmajor(good, device=DEV)])
+    torch.cuda.synchronize()
+    assert int(outs[0]["info"].cpu()[0]) == 1
+    assert int(outs[1]["info"].cpu()[0]) == 0
+
+
+def test_lensemble_dtype_mismatch(B):
+    L = torch.zeros((64, 64), dtype=torch.float64, device=DEV).t()
+    K = torch.zeros((64, 64), dtype=torch.float32, device=DEV).t()
+    with pytest.raises(ValueError):
+        B.dpp_lensemble_to_marginal_batched([L], Ks=[K])

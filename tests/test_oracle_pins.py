@@ -243,6 +243,51 @@ def test_prefix_run_matches_full_run():
     np.testing.assert_array_equal(full["pivots"][:p], pre["pivots"][:p])
 
 
+@pytest.mark.parametrize("which", ["ldlh", "lu"])
+def test_partial_run_leaves_the_conditional_kernel(which):
+    """After the first m decisions the trailing block of the in-place run is the
+    conditional marginal kernel of the rest (Props. 3-5), here from a library
+    solve; and sampling that block with the rest of the stream continues the
+    same chain (the full run's decisions for m..n-1, bit for bit)."""
+    n, m = 60, 23
+    K = (W.hermitian_kernel(n, seed=711) if which == "ldlh"
+         else W.similarity_kernel(n, seed=711)[0])
+    u = W.uniform_stream(n, seed=712)
+    A = np.array(K, dtype=np.float64, order="F", copy=True)
+    pre = SAMPLERS[which](A, u, npiv=m, inplace=True)
+    S_ref = oracle.conditional_kernel(K, pre["mask"][:m])
+    S = A[m:, m:]
+    if which == "ldlh":
+        S, S_ref = np.tril(S), np.tril(S_ref)
+    np.testing.assert_allclose(S, S_ref, rtol=0, atol=1e-12)
+    full = SAMPLERS[which](K, u)
+    rest = SAMPLERS[which](np.array(A[m:, m:], order="F"), u[m:])
+    assert np.array_equal(full["mask"][m:], rest["mask"])
+    np.testing.assert_array_equal(full["pivots"][m:], rest["pivots"])
+
+
+def test_conditional_kernel_of_no_decisions_is_k():
+    K = W.hermitian_kernel(9, seed=713)
+    np.testing.assert_array_equal(oracle.conditional_kernel(K, []), K)
+
+
+def test_lensemble_marginal_closed_forms():
+    """K = I - (L + I)^{-1} against three independent forms: the diagonal case
+    (K_jj = l_j / (1 + l_j)), the low-rank identity K = F (I + F^T F)^{-1} F^T
+    for L = F F^T, and the spectrum (eigenvalues l / (1 + l))."""
+    lam = np.array([0.0, 0.5, 1.0, 3.0, 100.0])
+    np.testing.assert_allclose(oracle.lensemble_marginal(np.diag(lam)), np.diag(lam / (1 + lam)),
+                               rtol=0, atol=1e-15)
+    rng = np.random.default_rng(714)
+    F = rng.normal(size=(40, 7))
+    L = F @ F.T
+    low = F @ np.linalg.solve(np.eye(7) + F.T @ F, F.T)
+    np.testing.assert_allclose(oracle.lensemble_marginal(L), low, rtol=0, atol=1e-12)
+    w = np.linalg.eigvalsh(L)
+    np.testing.assert_allclose(np.linalg.eigvalsh(oracle.lensemble_marginal(L)), w / (1 + w),
+                               rtol=0, atol=1e-12)
+
+
 def test_lda_larger_than_n_touches_only_the_matrix():
     """Column-major storage with lda > n: the padding rows are left alone."""
     import ctypes
