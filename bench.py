@@ -406,6 +406,55 @@ def bench_lensemble(torch, B, W, dev, count=4096):
                      "workspace_gb": round(ws.numel() / 1e9, 2)}
         del ws
         torch.cuda.empty_cache()
+
+    # On-device conversion of the same ensembles from their L (same draws,
+    # stored FP32): K_i = I - (L_i + I)^-1 in one batched call, against the
+    # kernels formed above on the host side in FP64.
+    del As, Aflat
+    Lflat = torch.empty_like(Kflat)
+    Cflat = torch.empty_like(Kflat)
+    Ls = [mat(Lflat, i) for i in range(count)]
+    Cs = [mat(Cflat, i) for i in range(count)]
+    for i in range(count):
+        W.lensemble_L(int(ns[i]), seed=400000 + i, out=Ls[i])
+    ws = torch.empty(B.dpp_lensemble_workspace_size([int(x) for x in ns]), dtype=torch.uint8,
+                     device=dev)
+    conv_out = []
+
+    def conv():
+        conv_out[:] = B.dpp_lensemble_to_marginal_batched(Ls, Ks=Cs, ws=ws)
+
+    ms = graph_time(torch, conv, reps=2)
+    out["conversion"] = {
+        "what": "K_i = I - (L_i + I)^-1 on the device (dpp_lensemble_to_marginal_batched, FP64 "
+                "arithmetic, FP32 storage), all 4096 in one call",
+        "ms_per_call": round(ms, 3),
+        "info_all_zero": all(int(o["info"].item()) == 0 for o in conv_out),
+        "max_abs_diff_vs_fp64_formed": float(torch.max(torch.abs(Cflat - Kflat)).item()),
+        "workspace_gb": round(ws.numel() / 1e9, 2)}
+    del ws, Lflat, Cflat, Ls, Cs, conv_out
+    torch.cuda.empty_cache()
+
+    # One large conversion against one FP64 sample of the same size (the paper
+    # expects the conversion to cost about three samples).
+    n = 8192
+    L = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+    W.lensemble_L(n, seed=410000, out=L)
+    K = torch.empty_like(L)
+    wsc = torch.empty(B.dpp_lensemble_workspace_size([n]), dtype=torch.uint8, device=dev)
+    ms_conv = graph_time(torch, lambda: B.dpp_lensemble_to_marginal_batched([L], Ks=[K], ws=wsc),
+                         reps=2)
+    del wsc
+    A = torch.empty_like(K)
+    u = torch.from_numpy(W.uniform_stream(n, seed=410001)).to(dev)
+    wss = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, [n], B.DPP_PREC_FP64),
+                      dtype=torch.uint8, device=dev)
+    ms_samp = graph_time(torch, lambda: B.dpp_sample_ldlh_batched([A], [u], prec=B.DPP_PREC_FP64,
+                                                                  ws=wss, Ks=[K]), reps=3)
+    out["conversion_n8192"] = {"ms": round(ms_conv, 3), "fp64_sample_ms": round(ms_samp, 3),
+                               "samples_worth": round(ms_conv / ms_samp, 2)}
+    del L, K, A, wss
+    torch.cuda.empty_cache()
     return out
 
 
