@@ -26,19 +26,23 @@ namespace leaf {
 
 constexpr int L = kLeaf;
 // Panel solves: 4 wavefronts per workgroup, each `gpw` groups of 16 panel rows
-// (or columns), gpw = 1..kGroups; a staged 16 x 64 tile per wavefront.
+// (or columns); a staged 16 x 64 tile per wavefront.
 constexpr int kWaves = 4;
-constexpr int kGroups = 4;
 constexpr int kThreads = kWaves * 64;
 constexpr int kTilePitch = 66;  // doubles per row of a staged 16 x 64 tile
 
 // Every workgroup of a diagonal-block launch first runs the 64-step chain,
 // then its share of the panel, one group of 16 rows after the other on each
-// wavefront. The launch takes as long as one chain plus one workgroup's
-// groups, as long as all workgroups are resident at once: so give each
-// wavefront the fewest groups that keep the grid within one resident round
-// (`per_cu` workgroups on each of the device's compute units), at most
-// kGroups. Returns the groups per wavefront; *gx receives the grid width.
+// wavefront. With W workgroups per problem and `per_cu` resident per compute
+// unit, the launch runs in rounds of cus * per_cu workgroups; each round costs
+// about one chain plus the groups of one wavefront. The groups per wavefront
+// (1 .. kMaxGroups) are chosen to minimize rounds * (chain + groups), with the
+// chain and the first group (load latency included) at about 34 us and each
+// further group at about 6 us (measured at n = 16384). A big batch of small
+// problems thus gets one workgroup per problem instead of several that would
+// each repeat the chain in later rounds. Returns the groups per wavefront;
+// *gx receives the grid width (workgroups per problem).
+constexpr int kMaxGroups = 16;
 inline int groups_per_wave(int64_t rows, int nprob, int per_cu, int* gx)
 {
     static int cus = 0;
@@ -50,15 +54,24 @@ inline int groups_per_wave(int64_t rows, int nprob, int per_cu, int* gx)
         else
             cus = 256;
     }
-    const int64_t resident = (int64_t)cus * per_cu;
-    int g = 1;
-    for (; g < kGroups; ++g) {
-        const int64_t w = (rows + kWaves * 16 * g - 1) / (kWaves * 16 * g);
-        if (w * nprob <= resident) break;
+    if (rows <= 0) {
+        *gx = 1;
+        return 1;
     }
-    const int64_t w = rows > 0 ? (rows + kWaves * 16 * g - 1) / (kWaves * 16 * g) : 1;
-    *gx = (int)w;
-    return g;
+    const int64_t resident = (int64_t)cus * per_cu;
+    int best = 1;
+    int64_t best_cost = INT64_MAX;
+    for (int g = 1; g <= kMaxGroups; ++g) {
+        const int64_t w = (rows + kWaves * 16 * g - 1) / (kWaves * 16 * g);
+        const int64_t rounds = (w * nprob + resident - 1) / resident;
+        const int64_t cost = rounds * (34 + 6 * (int64_t)g);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = g;
+        }
+    }
+    *gx = (int)((rows + kWaves * 16 * best - 1) / (kWaves * 16 * best));
+    return best;
 }
 
 __device__ __forceinline__ double readlane_d(double v, int lane)
