@@ -59,6 +59,21 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t NR, int64_t NC, bool 
     return true;
 }
 
+// Load through the global address space: a generic (flat) load also counts
+// against the LDS wait counter, so every LDS fragment wait would then wait for
+// the next chunk's operand loads as well.
+template <typename T>
+__device__ __forceinline__ double gload(const T* p)
+{
+    return (double)*(const __attribute__((address_space(1))) T*)(p);
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, double v)
+{
+    *(__attribute__((address_space(1))) T*)(p) = (T)v;
+}
+
 template <typename T, bool HERM>
 __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__ probs, Region rg,
                                                   int64_t k0, int kw)
@@ -106,31 +121,36 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     // Register staging of one chunk. A: thread -> (i = tid % 128, kk = tid/128 + 2q).
     // B (LDL^H): (j = tid % 128, kk = tid/128 + 2q), B[k][c] = L[c][k] * d'_k.
     // B (LU): (kk = tid % 16, j = tid/16 + 16q), B[k][c] = U[k][c] = A[k][c].
-    double ra[KC / 2], rb[KC / 2];
+    // The loads are unconditional (rows and columns past the region re-read
+    // the last one; they only feed accumulators that are never stored) and
+    // nothing uses their values before store_chunk, so they stay in flight
+    // during the current chunk's products; the pivot scaling of B happens at
+    // the store for the same reason.
+    double ra[KC / 2], rb[KC / 2], rp[KC / 2];
     auto load_chunk = [&](int kc) {
         {
-            const int i = tid & (TM - 1);
-            const int64_t gr = rowA0 + i;
+            const int64_t gr = rowA0 + (tid & (TM - 1)) < rEnd ? rowA0 + (tid & (TM - 1)) : rEnd - 1;
 #pragma unroll
             for (int q = 0; q < KC / 2; ++q) {
                 const int64_t gk = k0 + kc + (tid >> 7) + 2 * q;
-                ra[q] = (gr < rEnd) ? (double)A[gr + gk * lda] : 0.0;
+                ra[q] = gload(A + gr + gk * lda);
             }
         }
         if constexpr (HERM) {
-            const int j = tid & (TN - 1);
-            const int64_t gc = colB0 + j;
+            const int64_t gc = colB0 + (tid & (TN - 1)) < cEnd ? colB0 + (tid & (TN - 1)) : cEnd - 1;
 #pragma unroll
             for (int q = 0; q < KC / 2; ++q) {
                 const int64_t gk = k0 + kc + (tid >> 7) + 2 * q;
-                rb[q] = (gc < cEnd) ? (double)A[gc + gk * lda] * piv[gk] : 0.0;
+                rb[q] = gload(A + gc + gk * lda);
+                rp[q] = gload(piv + gk);
             }
         } else {
             const int64_t gk = k0 + kc + (tid & (KC - 1));
 #pragma unroll
             for (int q = 0; q < TN / 16; ++q) {
-                const int64_t gc = colB0 + (tid >> 4) + 16 * q;
-                rb[q] = (gc < cEnd) ? (double)A[gk + gc * lda] : 0.0;
+                const int64_t gc0 = colB0 + (tid >> 4) + 16 * q;
+                const int64_t gc = gc0 < cEnd ? gc0 : cEnd - 1;
+                rb[q] = gload(A + gk + gc * lda);
             }
         }
     };
@@ -139,7 +159,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
         for (int q = 0; q < KC / 2; ++q) sA[buf][(tid >> 7) + 2 * q][tid & (TM - 1)] = ra[q];
         if constexpr (HERM) {
 #pragma unroll
-            for (int q = 0; q < KC / 2; ++q) sB[buf][(tid >> 7) + 2 * q][tid & (TN - 1)] = rb[q];
+            for (int q = 0; q < KC / 2; ++q) sB[buf][(tid >> 7) + 2 * q][tid & (TN - 1)] = rb[q] * rp[q];
         } else {
 #pragma unroll
             for (int q = 0; q < TN / 16; ++q) sB[buf][tid & (KC - 1)][(tid >> 4) + 16 * q] = rb[q];
@@ -193,7 +213,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
             for (int e = 0; e < 4; ++e) {
                 const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
                 const bool ok = gr < rEnd && gc < cEnd && (!HERM || gr >= gc);
-                cv[bj][e] = ok ? (double)srcp[gc * lds_] : 0.0;
+                cv[bj][e] = ok ? gload(srcp + gc * lds_) : 0.0;
             }
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
@@ -201,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
             for (int e = 0; e < 4; ++e) {
                 const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
                 const bool ok = gr < rEnd && gc < cEnd && (!HERM || gr >= gc);
-                if (ok) rowp[gc * lda] = (T)(cv[bj][e] - acc[bi][bj][e]);
+                if (ok) gstore(rowp + gc * lda, cv[bj][e] - acc[bi][bj][e]);
             }
     }
 }
