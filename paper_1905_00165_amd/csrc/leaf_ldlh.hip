@@ -106,13 +106,22 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
                 const double l1 = c1 / dp1;
                 sB2[lane] = make_double2(c, c1);
                 __builtin_amdgcn_wave_barrier();
+                // Broadcast reads in batches of 16, all issued before their
+                // FMAs, so up to 15 are in flight (left to itself the
+                // compiler keeps two or three, and the chain waits on each).
 #pragma unroll
-                for (int k = 0; k < L; ++k)
-                    if (k > j + 1) {
-                        const double2 v = sB2[k];  // A[k][j], A[k][j+1]
-                        a[k] -= l * v.x;
-                        a[k] -= l1 * v.y;
-                    }
+                for (int kb = 0; kb < L; kb += 16) {
+                    double2 v[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (kb + i > j + 1) v[i] = sB2[kb + i];  // A[k][j], A[k][j+1]
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (kb + i > j + 1) {
+                            a[kb + i] -= l * v[i].x;
+                            a[kb + i] -= l1 * v[i].y;
+                        }
+                }
                 // No LDS access moves across this point: hoisting the next
                 // step's reads would hold them in registers and spill.
                 asm volatile("" ::: "memory");
