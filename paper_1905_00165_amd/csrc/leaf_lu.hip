@@ -95,9 +95,22 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
                 __builtin_amdgcn_wave_barrier();
                 // Rows at or above the pivot keep their entries (rows of U).
                 const double l = below ? a[j] / dp : 0.0;
+                // Broadcast reads in batches of 16, all issued before their
+                // FMAs (up to 15 in flight instead of the two or three the
+                // compiler keeps on its own).
 #pragma unroll
-                for (int k = 0; k < L; ++k)
-                    if (k > j) a[k] -= l * sB[k];
+                for (int kb = 0; kb < L; kb += 16) {
+                    double v[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (kb + i > j) v[i] = sB[kb + i];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (kb + i > j) a[kb + i] -= l * v[i];
+                }
+                // No LDS access moves across this point: hoisting the next
+                // step's reads would hold them in registers and spill.
+                asm volatile("" ::: "memory");
                 __builtin_amdgcn_wave_barrier();
                 a[j] = isj ? dp : (below ? l : a[j]);
                 mydp = isj ? dp : mydp;
