@@ -141,6 +141,14 @@ def run_path(torch, B, K, us, prec, args, As, ws):
     t1 = time.perf_counter()
     sizes = [int(o["mask"].sum().item()) for o in outs]
     infos = [int(o["info"].item()) for o in outs]
+    # Diagnostics of the decisions: the smallest |u_j - d_j| over the samples
+    # (how close any decision came to a tie) and the count of pre-decision
+    # probabilities outside [-1e-12, 1 + 1e-12] (rounding past [0, 1]).
+    margin, out_of_range = float("inf"), 0
+    for o, u in zip(outs, us):
+        d = o["pivots"] + 1.0 - o["mask"].to(torch.float64)
+        margin = min(margin, float(torch.min(torch.abs(u[:n] - d)).item()))
+        out_of_range += int(((d < -1e-12) | (d > 1.0 + 1e-12)).sum().item())
     if graph is not None:
         B.dpp_profile_begin()
         step()
@@ -162,6 +170,7 @@ def run_path(torch, B, K, us, prec, args, As, ws):
         "tflops": samples * flops_per_sample / (wall_ms * 1e-3) / 1e12,
         "kernel_ms_per_sample": lib_ms / prof_samples,
         "sizes": sizes, "infos": infos, "profile": prof,
+        "min_margin": margin, "d_out_of_range": out_of_range,
         "event_ms": ev0.elapsed_time(ev1),
     }
 
@@ -217,7 +226,16 @@ def cpu_baseline(K_host, u0, n, seconds):
     j = np.arange(n, dtype=np.float64)
     frac = float(np.sum((n - j[:p]) ** 2) / np.sum((n - j) ** 2))
     sps = frac / t
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": sps, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "affinity_cpus": len(os.sched_getaffinity(0)),
             "sample": f"first {p} of {n} pivots of one sample (unblocked FP64 LDL^H, "
                       f"{frac * 100:.3f}% of the n^3/3 work) in {t:.1f} s, scaled by that fraction",
             "gflops": sps * n ** 3 / 3.0 / 1e9}
@@ -558,8 +576,8 @@ def main():
         "dtype": "bf16" if order[0] == "split" else "f64",
         "data": "synthetic",
         "config": {"workload": f"projection kernel K = Q_r Q_r^T, n={n}, rank={r}, FP64 storage; "
-                               f"LDL^H sampler, {bsz} samples per step (one batched call), "
-                               f"lower triangle of the working copy restored from K inside each step",
+                               f"LDL^H sampler, {bsz} samples per step (one batched call reading the "
+                               f"resident K out of place, each sample's factor to its own buffer)",
                    "n": n, "rank": r, "batch": bsz,
                    "precision": "split_bf16x3" if order[0] == "split" else "fp64",
                    "launch": "eager" if args.no_graph else "HIP graph replay of one step"},
@@ -575,6 +593,8 @@ def main():
                      "kernel_ms_per_sample": round(h["kernel_ms_per_sample"], 3),
                      "invariant_size_eq_rank": all(s == r for s in h["sizes"]),
                      "info_all_zero": all(i == 0 for i in h["infos"]),
+                     "min_abs_u_minus_d": h["min_margin"],
+                     "pre_decision_d_outside_0_1": h["d_out_of_range"],
                      "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
                                  for k, v in h["profile"].items()}}
     if "split" in res and "fp64" in res:
@@ -585,6 +605,13 @@ def main():
                                      PEAK_BF16 if order[0] == "split" else PEAK_FP64)
     if out["roofline"] is not None:
         out["roofline"]["traffic"] = measured_traffic(dom, n, bsz)
+        if order[0] == "split":
+            # The split update issues three BF16 products per algorithmic one,
+            # so 1/3 of the peak is its ceiling on the algorithmic count.
+            rl = out["roofline"]
+            rl["mfma_issued_tflops"] = round(3 * rl["achieved"], 3)
+            rl["mfma_issued_frac"] = round(3 * rl["frac"], 4)
+            rl["algorithmic_ceiling_frac"] = round(1.0 / 3.0, 4)
     if "fp64" in res and order[0] != "fp64":
         out["roofline_fp64"] = roofline_entry(res["fp64"]["profile"], "update_f64", PEAK_FP64)
 
