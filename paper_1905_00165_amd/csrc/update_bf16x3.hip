@@ -72,7 +72,7 @@ struct Shape {
     static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
 };
 using Wide = Shape<256, 256, 2, 4, 1, 1, 16, 4>;
-using Medium = Shape<256, 128, 2, 2, 1, 2, 32, 2>;
+using Medium = Shape<256, 128, 2, 2, 2, 1, 16, 3>;
 using Narrow = Shape<128, 64, 4, 1, 3, 1, 32, 2>;
 
 // XOR swizzle of the 16-byte segments of LDS row r. A fragment read (lane l:
