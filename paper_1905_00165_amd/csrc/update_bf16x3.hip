@@ -33,6 +33,8 @@
 // tiles are ordered by groups of 4 tile columns, row by row within a group, so
 // the ~32 tiles an XCD runs at once form an 8x4 block that shares 8 row panels
 // and 4 column panels in that XCD's L2.
+#include <atomic>
+
 #include "dpp_internal.h"
 
 namespace dpp {
@@ -458,12 +460,17 @@ hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t 
     const int64_t tiles = (HERM && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
     const unsigned grid_x = (unsigned)((tiles + 7) / 8 * 8);  // XCD remap needs a multiple of 8
     auto k = update_bf16x3<T, HERM, S>;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // The dynamic-LDS limit is a per-device function attribute: set it once
+    // on each device the kernel runs on.
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
+    if (!bit || !(attr_set.load() & bit)) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.fetch_or(bit);
     }
     hipLaunchKernelGGL(k, dim3(grid_x, nprob), dim3(S::THREADS), S::LDS, s, probs, rg, k0, kw, j0,
                        ss);
