@@ -142,3 +142,56 @@ def test_lensemble_dtype_mismatch(B):
     K = torch.zeros((64, 64), dtype=torch.float32, device=DEV).t()
     with pytest.raises(ValueError):
         B.dpp_lensemble_to_marginal_batched([L], Ks=[K])
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=lambda p: PREC_ID[p])
+def test_partial_out_of_place_equals_partial_in_place(B, prec):
+    """npiv together with a read-only source K: the decided prefix, the
+    trailing conditional kernel and the factor are those of the in-place
+    partial run, bit for bit, and K is unchanged."""
+    n, m = 900, 320
+    K = W.hermitian_kernel(n, seed=970)
+    u = torch.from_numpy(W.uniform_stream(n, seed=971)).to(DEV)
+    src = B.colmajor(K, device=DEV)
+    before = src.cpu().numpy().copy()
+    A_in = B.colmajor(K, device=DEV)
+    A_out = torch.full((n, n), float("nan"), dtype=torch.float64, device=DEV).t()
+    o_in = B.dpp_sample_ldlh_batched([A_in], [u], prec=prec, npivs=[m])[0]
+    o_out = B.dpp_sample_ldlh_batched([A_out], [u], prec=prec, npivs=[m], Ks=[src])[0]
+    torch.cuda.synchronize()
+    for key in ("mask", "pivots"):      # entries past npiv are not written
+        assert torch.equal(o_in[key][:m], o_out[key][:m]), key
+    for key in ("loglik", "info"):
+        assert torch.equal(o_in[key], o_out[key]), key
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(A_in.cpu().numpy()[low], A_out.cpu().numpy()[low])
+    assert np.array_equal(src.cpu().numpy(), before)
+
+
+def test_lensemble_conversion_graph_replays(B):
+    """The conversion captured in a HIP graph and replayed (with eager work
+    in between) gives the eager result every time."""
+    ns = [100, 300, 64]
+    Ls = [B.colmajor(W.lensemble_L(n, seed=980 + i), device=DEV) for i, n in enumerate(ns)]
+    Ks = [torch.empty_like(L) for L in Ls]
+    ws = torch.empty(B.dpp_lensemble_workspace_size(ns), dtype=torch.uint8, device=DEV)
+    B.dpp_lensemble_to_marginal_batched(Ls, Ks=Ks, ws=ws)
+    torch.cuda.synchronize()
+    ref = [K.clone() for K in Ks]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.dpp_lensemble_to_marginal_batched(Ls, Ks=Ks, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.dpp_lensemble_to_marginal_batched(Ls, Ks=Ks, ws=ws)
+    for _ in range(3):
+        for K in Ks:
+            K.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for K, R in zip(Ks, ref):
+            assert torch.equal(K, R)
