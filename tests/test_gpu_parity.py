@@ -167,6 +167,33 @@ def test_lda_padding_untouched():
     assert v.ok, v.why
 
 
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_largest_leading_dimension(herm, prec):
+    """lda = 2^20, the documented maximum (strips of 256 columns then span
+    just under 2^31 bytes): the results match the oracle and sampled padding
+    entries are untouched."""
+    n, lda = 300, 1 << 20
+    K = W.hermitian_kernel(n, seed=14) if herm else W.similarity_kernel(n, seed=14)[0]
+    u = W.uniform_stream(n, seed=1400)
+    storage = torch.full((n, lda), 3.0, dtype=torch.float64, device=DEV)
+    storage[:, :n] = torch.as_tensor(np.ascontiguousarray(K.T), device=DEV)
+    A = storage.t()[:n, :]
+    assert A.stride() == (1, lda)
+    fn = B.dpp_sample_ldlh if herm else B.dpp_sample_lu
+    out = fn(A, torch.from_numpy(u).to(DEV), prec=prec)
+    torch.cuda.synchronize()
+    ref = (oracle.ldlh if herm else oracle.lu)(K, u)
+    tol, thr = TOL[prec]
+    v = compare(out["mask"].cpu().numpy(), out["pivots"].cpu().numpy(),
+                float(out["loglik"].cpu()[0]), ref, u, tol, thr)
+    assert int(out["info"].cpu()[0]) == 0
+    assert v.ok, v.why
+    cols = torch.tensor([n, n + 1, 4096, lda // 2, lda - 1], device=DEV)
+    assert bool(torch.all(storage[:, cols] == 3.0))
+    del storage
+
+
 @pytest.mark.parametrize("ns", [[100, 257, 64, 1], [700, 1000, 300, 129, 1100]],
                          ids=["small", "uneven"])
 @pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
