@@ -1,0 +1,117 @@
+"""Batched calls of at least 64 problems in several size groups run the groups
+on the caller's stream and on helper streams forked from it and joined back.
+These tests check that this changes no result: against single calls, under
+graph capture and replay, and with two callers' streams running such batches
+at the same time."""
+import pytest
+
+from paper_1905_00165_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+SIZES = [64, 130, 300, 700, 1000, 129, 1100, 257]    # six size groups
+NS = SIZES * 8                                        # 64 problems
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_00165_amd import binding
+    return binding
+
+
+def _problems(B, seed):
+    """64 problems; the eight of one size share one read-only K (out of place)
+    and differ in their uniforms."""
+    base = {n: B.colmajor(W.hermitian_kernel(n, seed=seed + i), device=DEV)
+            for i, n in enumerate(SIZES)}
+    Ks = [base[n] for n in NS]
+    us = [torch.from_numpy(W.uniform_stream(n, seed=1000 * seed + i)).to(DEV) for i, n in enumerate(NS)]
+    As = [torch.empty_like(K) for K in Ks]
+    outs = [{"mask": torch.empty(n, dtype=torch.uint8, device=DEV),
+             "pivots": torch.empty(n, dtype=torch.float64, device=DEV),
+             "loglik": torch.empty(1, dtype=torch.float64, device=DEV),
+             "info": torch.empty(1, dtype=torch.int32, device=DEV)} for n in NS]
+    return Ks, us, As, outs
+
+
+def _snapshot(As, outs):
+    # LDL^H writes the lower triangle of A only.
+    return [(torch.tril(A), o["mask"].clone(), o["pivots"].clone(), o["loglik"].clone(), o["info"].clone())
+            for A, o in zip(As, outs)]
+
+
+def _poison(As, outs):
+    for A, o in zip(As, outs):
+        A.fill_(0.5)
+        o["mask"].fill_(7)
+        o["pivots"].fill_(-3.0)
+        o["loglik"].fill_(0.0)
+        o["info"].fill_(-1)
+
+
+def _equal(a, b):
+    return all(torch.equal(x, y) for s, t in zip(a, b) for x, y in zip(s, t))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "split"])
+def test_helper_lanes_equal_single_calls_and_replay(B, prec):
+    """The 64-problem batch equals single calls (one problem per size), and a
+    graph of it captured on another stream replays that result bit for bit,
+    with eager calls in between."""
+    Ks, us, As, outs = _problems(B, seed=60)
+    ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, NS, prec), dtype=torch.uint8,
+                     device=DEV)
+    call = lambda: B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, outs=outs, Ks=Ks)
+    call()
+    torch.cuda.synchronize()
+    ref = _snapshot(As, outs)
+    for o in outs:
+        assert int(o["info"].item()) == 0
+    for i in range(len(SIZES)):
+        A1 = torch.empty_like(Ks[i])
+        s = B.dpp_sample_ldlh_batched([A1], [us[i]], prec=prec, Ks=[Ks[i]])[0]
+        torch.cuda.synchronize()
+        assert _equal(_snapshot([A1], [s]), ref[i:i + 1]), NS[i]
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        call()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        _poison(As, outs)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert _equal(_snapshot(As, outs), ref), rep
+        call()                                   # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_two_callers_streams_at_once(B):
+    """Two 64-problem batches issued on two streams without a sync between
+    them give the results each gives alone."""
+    sets = [_problems(B, seed=70), _problems(B, seed=80)]
+    wss = [torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, NS, 1), dtype=torch.uint8,
+                       device=DEV) for _ in sets]
+    alone = []
+    for (Ks, us, As, outs), ws in zip(sets, wss):
+        B.dpp_sample_ldlh_batched(As, us, prec=1, ws=ws, outs=outs, Ks=Ks)
+        torch.cuda.synchronize()
+        alone.append(_snapshot(As, outs))
+        _poison(As, outs)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in sets]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    for st, (Ks, us, As, outs), ws in zip(streams, sets, wss):
+        with torch.cuda.stream(st):
+            B.dpp_sample_ldlh_batched(As, us, prec=1, ws=ws, outs=outs, Ks=Ks)
+    torch.cuda.synchronize()
+    for (Ks, us, As, outs), ref in zip(sets, alone):
+        assert _equal(_snapshot(As, outs), ref)
