@@ -159,10 +159,20 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Where T[k][t] sits in LDS: Tt[t * LD + k] (T stored by columns with pitch
+// LD), or with TR, Tt[k * LD + t] (T stored by rows, e.g. the transpose of an
+// upper triangle stored by columns).
+template <int LD, bool TR>
+__device__ __forceinline__ int tidx(int t, int k)
+{
+    return TR ? k * LD + t : t * LD + k;
+}
+
 // One group of 16 rows. Lane (q, i16) = (lane / 16, lane % 16) holds in
 // cur[4b + e] row i16, column 16b + 4e + q of A and receives the same entry
-// of X in x[b][e]. Tt[t * 64 + k] = T[k][t] (T's columns, or equivalently the
-// rows of T^T); Inv[b * 256 + i * 16 + k] = (T_bb^{-1})[i][k].
+// of X in x[b][e]. T[k][t] is Tt[tidx<LD, TR>(t, k)]; only the blocks below
+// the diagonal blocks are read. Inv[b * 256 + i * 16 + k] = (T_bb^{-1})[i][k].
+template <int LD = L, bool TR = false>
 __device__ __forceinline__ void solve_group(const double* Tt, const double* Inv,
                                             const double (&cur)[16], d4 (&x)[4], int q, int i16)
 {
@@ -173,7 +183,7 @@ __device__ __forceinline__ void solve_group(const double* Tt, const double* Inv,
         for (int c = 0; c < b; ++c)
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                acc = mfma16(-Tt[(16 * c + 4 * s + q) * L + 16 * b + i16], x[c][s], acc);
+                acc = mfma16(-Tt[tidx<LD, TR>(16 * c + 4 * s + q, 16 * b + i16)], x[c][s], acc);
         d4 xb = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < 4; ++s) xb = mfma16(Inv[b * 256 + i16 * 16 + 4 * s + q], acc[s], xb);
@@ -181,10 +191,10 @@ __device__ __forceinline__ void solve_group(const double* Tt, const double* Inv,
     }
 }
 
-// Inverses of the four 16x16 diagonal blocks of T (lower triangular; unit
-// diagonal if UNIT, else the diagonal Tt[(16b+k) * 65]) by forward
-// substitution, one column per lane of the calling wavefront.
-template <bool UNIT>
+// Inverses of the four 16x16 diagonal blocks of T (lower triangular, unit
+// diagonal if UNIT; T[k][t] = Tt[tidx<LD, TR>(t, k)] as for solve_group) by
+// forward substitution, one column per lane of the calling wavefront.
+template <bool UNIT, int LD = L, bool TR = false>
 __device__ __forceinline__ void invert_diag_blocks(const double* Tt, double* Inv, int lane)
 {
     const int b = lane >> 4, c = lane & 15;
@@ -193,8 +203,8 @@ __device__ __forceinline__ void invert_diag_blocks(const double* Tt, double* Inv
     for (int k = 0; k < 16; ++k) {
         double acc = (k == c) ? 1.0 : 0.0;
 #pragma unroll
-        for (int t = 0; t < k; ++t) acc -= Tt[(16 * b + t) * L + 16 * b + k] * y[t];
-        y[k] = UNIT ? acc : acc / Tt[(16 * b + k) * (L + 1)];
+        for (int t = 0; t < k; ++t) acc -= Tt[tidx<LD, TR>(16 * b + t, 16 * b + k)] * y[t];
+        y[k] = UNIT ? acc : acc / Tt[tidx<LD, TR>(16 * b + k, 16 * b + k)];
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) Inv[b * 256 + k * 16 + c] = y[k];

@@ -8,8 +8,9 @@ using namespace leaf;
 
 // ---------------------------------------------------------------------- LU
 // Step 1 (wavefront 0, every workgroup): the unblocked sampler on the 64x64
-// diagonal block, one block row per lane; at pivot j the row of U is
-// broadcast through LDS and the rows below take the rank-one update.
+// diagonal block, one block row per lane; at pivot j the row of U (lane j's
+// registers) is broadcast by readlane and the rows below take the rank-one
+// update.
 //
 // Step 2: both panels, with the factored block L11 (unit lower) and U11
 // (upper, the modified pivots on its diagonal), each as solves X T^T = A of
@@ -21,11 +22,20 @@ using namespace leaf;
 // The row panel's columns are contiguous in memory; they pass through the
 // wavefront's LDS tile so that loads and stores stay coalesced. A receives L21
 // and U12; the split planes, hi/lo of L21 by row and of U12^T by column.
-// Each workgroup takes 256 rows of the column panel and 256 columns of the
-// row panel (splitting them over separate workgroups measured slower: the
-// chain, repeated per workgroup, dominates).
+// Each workgroup takes the same number of rows of the column panel and
+// columns of the row panel (splitting them over separate workgroups measured
+// slower: the chain, repeated per workgroup, dominates).
+//
+// LDS holds the factored block once, packed as the chain leaves it (strict
+// lower part L11, upper part U11, by columns with pitch kLP: the row panel
+// reads L11 by columns, the column panel U11^T, i.e. the same array by rows;
+// the odd pitch keeps both access patterns free of bank conflicts), and one
+// set of diagonal-block inverses, those of U11^T for the column panel, then
+// those of L11 for the row panel: 75 KiB, two workgroups per CU.
+constexpr int kLP = L + 1;
+
 template <typename T, bool SPLIT>
-__global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
+__global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
                                              int64_t j0, int ss, int gpw)
 {
     const DevProb P = probs[blockIdx.y];
@@ -40,17 +50,12 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
     int64_t lds;  // leading dimension of the source the loads read (K at column 0)
     const T* __restrict__ S = first_source<T>(P, c0 == 0, lds);
 
-    // sT (the tiles) comes first; the chain's broadcast row sB borrows it.
-    // The triangles as Tt[t*L + k] = T[k][t] for solve_group: the row panel
-    // uses T = L11 (sL[t*L + k] = L11[k][t], k > t), the column panel
-    // T = U11^T (sU[t*L + k] = U11[t][k], k >= t); zero elsewhere.
-    __shared__ double smem[kWaves * 16 * kTilePitch + 2 * L * L + 2 * 4 * 16 * 16];
+    // sP[k + t*kLP] = entry (k, t) of the factored block: L11[k][t] for k > t,
+    // U11[k][t] for k <= t.
+    __shared__ double smem[kWaves * 16 * kTilePitch + L * kLP + 4 * 16 * 16];
     double* const sT = smem;
-    double* const sB = smem;                         // chain only
-    double* const sL = smem + kWaves * 16 * kTilePitch;
-    double* const sU = sL + L * L;
-    double* const sIL = sU + L * L;                  // inverses of the diagonal blocks of L11
-    double* const sIU = sIL + 4 * 16 * 16;           // ... and of U11^T
+    double* const sP = smem + kWaves * 16 * kTilePitch;
+    double* const sI = sP + L * kLP;                 // inverses of the diagonal blocks
 
     const int tid = threadIdx.x;
     if (tid < L) {
@@ -87,29 +92,22 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
                 const bool keep = uj < d;                // Bernoulli(d) with stream u_j
                 const double dp = keep ? d : d - 1.0;   // Prop. 4 on rejection
                 const bool isj = me == j, below = me > j;
-                if (isj) {
-#pragma unroll
-                    for (int k = 0; k < L; ++k)
-                        if (k > j) sB[k] = a[k];  // row j of U
-                }
-                __builtin_amdgcn_wave_barrier();
                 // Rows at or above the pivot keep their entries (rows of U).
                 const double l = below ? a[j] / dp : 0.0;
-                // Broadcast reads in batches of 16, all issued before their
-                // FMAs (up to 15 in flight instead of the two or three the
-                // compiler keeps on its own).
+                // Row j of U lives in lane j's registers: it is read lane by
+                // lane with readlane (into scalar registers), 16 entries ahead
+                // of their FMAs. Writing it to LDS from the one lane and
+                // reading it back took 35 instead of 21 us per chain.
 #pragma unroll
                 for (int kb = 0; kb < L; kb += 16) {
                     double v[16];
 #pragma unroll
                     for (int i = 0; i < 16; ++i)
-                        if (kb + i > j) v[i] = sB[kb + i];
+                        if (kb + i > j) v[i] = readlane_d(a[kb + i], j);
 #pragma unroll
                     for (int i = 0; i < 16; ++i)
                         if (kb + i > j) a[kb + i] -= l * v[i];
                 }
-                // No LDS access moves across this point: hoisting the next
-                // step's reads would hold them in registers and spill.
                 asm volatile("" ::: "memory");
                 __builtin_amdgcn_wave_barrier();
                 a[j] = isj ? dp : (below ? l : a[j]);
@@ -119,10 +117,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
         }
 
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            sL[k * L + lane] = (k < lane && lane < bs) ? a[k] : 0.0;
-            sU[lane * L + k] = (k >= lane && lane < bs) ? a[k] : (k == lane ? 1.0 : 0.0);
-        }
+        for (int k = 0; k < L; ++k) sP[lane + k * kLP] = lane < bs ? a[k] : (k == lane ? 1.0 : 0.0);
 
         // The factored block goes to the workspace strip, not to A: other
         // workgroups of this launch may still be loading the original block
@@ -141,17 +136,15 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
     // full 64 wide (a ragged block is the last one), so bs == L from here on.
     if (idx0 >= n) return;
 
-    // U11^T is lower triangular with the pivots on its diagonal; L11 has a
-    // unit diagonal.
-    if (tid < 64) invert_diag_blocks<true>(sL, sIL, tid);
-    else if (tid < 128) invert_diag_blocks<false>(sU, sIU, tid - 64);
+    // U11^T is lower triangular with the pivots on its diagonal.
+    if (tid < 64) invert_diag_blocks<false, kLP, true>(sP, sI, tid);
     __syncthreads();
 
     const int lane = tid & 63;
     const int q = lane >> 4, i16 = lane & 15;
     const int64_t w0 = idx0 + (int64_t)(tid >> 6) * (16 * gpw);
-    if (w0 >= n) return;
-    const int ngroups = (int)((n - w0 + 15) / 16) < gpw ? (int)((n - w0 + 15) / 16) : gpw;
+    // A wavefront without rows still takes part in the barriers below.
+    const int ngroups = w0 >= n ? 0 : ((int)((n - w0 + 15) / 16) < gpw ? (int)((n - w0 + 15) / 16) : gpw);
     double* const tile = sT + (tid >> 6) * (16 * kTilePitch);
     const int cstride = (int)(lda * (int64_t)sizeof(T));
     const int istride = (int)(lds * (int64_t)sizeof(T));
@@ -184,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
     };
 
     // ---- column panel: rows w0 + 16g + i16 of columns [c0, c0+64) ----------
-    {
+    if (ngroups > 0) {
         const __amdgpu_buffer_rsrc_t rs =
             strip_rsrc(A + w0 + c0 * lda, (int64_t)L * lda * (int64_t)sizeof(T));
         const __amdgpu_buffer_rsrc_t rsi =
@@ -209,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
                 for (int k = 0; k < 16; ++k) nxt[k] = buf_load<T>(rsi, v, 4 * k * istride);
             }
             d4 x[4];
-            solve_group(sU, sIU, cur, x, q, i16);  // L21 = A21 U11^{-1}
+            solve_group<kLP, true>(sP, sI, cur, x, q, i16);  // L21 = A21 U11^{-1}
             if (w0 + 16 * g + i16 < n) {
                 const int v = row_of(g) + q * cstride;
 #pragma unroll
@@ -229,16 +222,32 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
         }
     }
 
+    // The inverses of L11's diagonal blocks replace those of U11^T once every
+    // wavefront is done with the column panel.
+    __syncthreads();
+    if (tid < 64) invert_diag_blocks<true, kLP, false>(sP, sI, tid);  // L11: unit diagonal
+    __syncthreads();
+
     // ---- row panel: columns w0 + 16g + i of rows [c0, c0+64) ---------------
     // Lane l moves column l/4, entries 16(l%4) + [0, 16), through the tile.
-    {
+    // The next group's loads are issued before the current group's solve;
+    // they are unconditional (columns past n re-read the last one, whose
+    // results are not stored).
+    if (ngroups > 0) {
         const int tcl = lane >> 2, tk = 16 * (lane & 3);
+        auto load_cols = [&](int g, double (&dst)[16]) {
+            const int64_t col = w0 + 16 * g + tcl;
+            const T* src = S + c0 + (col < n ? col : n - 1) * lds + tk;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) dst[k] = (double)src[k];
+        };
+        double nxt[16];
+        load_cols(0, nxt);
         for (int g = 0; g < ngroups; ++g) {
             const int64_t col = w0 + 16 * g + tcl;
-            const T* src = S + c0 + col * lds + tk;
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                tile[tcl * kTilePitch + tk + k] = col < n ? (double)src[k] : 0.0;
+            for (int k = 0; k < 16; ++k) tile[tcl * kTilePitch + tk + k] = nxt[k];
+            if (g + 1 < ngroups) load_cols(g + 1, nxt);
             __builtin_amdgcn_wave_barrier();
             double cur[16];
 #pragma unroll
@@ -247,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void leaf_lu(const DevProb* __restrict__ 
                 for (int e = 0; e < 4; ++e) cur[4 * b + e] = tile[i16 * kTilePitch + 16 * b + 4 * e + q];
             __builtin_amdgcn_wave_barrier();
             d4 x[4];
-            solve_group(sL, sIL, cur, x, q, i16);  // U12^T = A12^T L11^{-T}
+            solve_group<kLP, false>(sP, sI, cur, x, q, i16);  // U12^T = A12^T L11^{-T}
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -269,7 +278,7 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
                     int64_t j0, int ss, hipStream_t s)
 {
     int gx = 1;
-    const int gpw = groups_per_wave(nmax - c0 - L, nprob, 1, &gx);  // one workgroup per CU (LDS)
+    const int gpw = groups_per_wave(nmax - c0 - L, nprob, 1, &gx);
     dim3 grid(gx, nprob), block(kThreads);
     if (split) hipLaunchKernelGGL((leaf_lu<T, true>), grid, block, 0, s, probs, c0, j0, ss, gpw);
     else hipLaunchKernelGGL((leaf_lu<T, false>), grid, block, 0, s, probs, c0, j0, ss, gpw);
