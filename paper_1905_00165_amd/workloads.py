@@ -21,6 +21,14 @@ def uniform_stream(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).random(n)
 
 
+def greedy_stream(n: int) -> np.ndarray:
+    """u_j = 1/2 for every index. With the keep-iff-u_j-below-d_j rule each
+    index then takes its likelier outcome given the earlier decisions: the
+    greedy maximum-likelihood mode (Sec. 2, after Thm. 2); an exact tie
+    d_j = 1/2 excludes j."""
+    return np.full(n, 0.5)
+
+
 def symmetrize_lower(K: np.ndarray) -> np.ndarray:
     """Copy the lower triangle onto the upper one, so K is exactly symmetric."""
     return np.tril(K) + np.tril(K, -1).T

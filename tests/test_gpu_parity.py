@@ -80,6 +80,21 @@ def test_lu_small_sizes(n, prec):
     _check(False, K, u, prec)
 
 
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_greedy_mode(herm, prec):
+    """u = 1/2 everywhere (greedy maximum-likelihood mode): the decisions,
+    pivots and log-likelihood match the oracle's greedy run at n = 700 (ten
+    full blocks and a ragged one), Hermitian K and a diagonal similarity of it."""
+    n = 700
+    K = W.hermitian_kernel(n, seed=16)
+    if not herm:
+        s = np.exp(np.random.default_rng(17).normal(0.0, 0.5, size=n))
+        K = np.asfortranarray((s[:, None] * K) / s[None, :])
+    v, got, _ = _check(herm, K, W.greedy_stream(n), prec)
+    assert 0 < int(got["mask"].sum()) < n
+
+
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
 def test_ldlh_dense_kernel_n1024_streams(prec):
     """The plain workload at n = 1024: K = Q diag(lam) Q^T, lam ~ U(0,1)."""

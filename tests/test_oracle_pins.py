@@ -94,6 +94,42 @@ def test_single_index():
 # ------------------------------------------------------------ exact enumeration
 
 @pytest.mark.parametrize("which", ["ldlh", "lu"])
+def test_greedy_mode_takes_the_likelier_outcome(which):
+    """u = 1/2 everywhere (greedy maximum-likelihood mode, Sec. 2): at each
+    index the oracle keeps j iff j's inclusion probability given the earlier
+    decisions exceeds 1/2. That probability comes from library determinants
+    of leading principal submatrices, P[Y ∩ [0, m) = S] = |det(K_m - 1_{[0,m) - S})|
+    (the DPP restricted to [0, m) has kernel K_m), as a ratio of the prefix
+    with and without j kept; the pivots are that probability (kept) or it
+    minus 1, and the log-likelihood sums the logs of the likelier outcomes."""
+    n = 10
+    K = W.hermitian_kernel(n, seed=33)       # eigenvalues U(0, 1): both outcomes occur
+    if which == "lu":                        # a diagonal similarity of it (Prop. 2)
+        s = np.exp(np.random.default_rng(34).normal(0.0, 0.5, size=n))
+        K = (s[:, None] * K) / s[None, :]
+    res = SAMPLERS[which](K, W.greedy_stream(n))
+
+    def prefix_prob(bits):
+        m = len(bits)
+        if m == 0:
+            return 1.0
+        return abs(np.linalg.det(K[:m, :m] - np.diag(1.0 - np.asarray(bits, dtype=np.float64))))
+
+    bits, ll, margin = [], 0.0, 1.0
+    for j in range(n):
+        p = prefix_prob(bits + [1]) / prefix_prob(bits)
+        take = p > 0.5
+        margin = min(margin, abs(p - 0.5))
+        assert res["mask"][j] == int(take), j
+        assert res["pivots"][j] == pytest.approx(p if take else p - 1.0, abs=1e-12)
+        ll += np.log(max(p, 1.0 - p))
+        bits.append(int(take))
+    assert margin > 1e-6             # no decision here rests on rounding
+    assert 0 < sum(bits) < n
+    assert res["loglik"] == pytest.approx(ll, rel=1e-12)
+
+
+@pytest.mark.parametrize("which", ["ldlh", "lu"])
 def test_forced_streams_enumerate_the_dpp_law(which):
     """For every S of [8]: the forced stream returns S with likelihood
     |det(K - 1_{S^c})| (library determinant), and the 2^8 likelihoods sum to 1.
