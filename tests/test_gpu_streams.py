@@ -23,10 +23,12 @@ def B():
     return binding
 
 
-def _problems(B, seed):
+def _problems(B, seed, herm=True):
     """64 problems; the eight of one size share one read-only K (out of place)
-    and differ in their uniforms."""
-    base = {n: B.colmajor(W.hermitian_kernel(n, seed=seed + i), device=DEV)
+    and differ in their uniforms. Hermitian K, or for LU a non-symmetric
+    kernel of the same law (a diagonal similarity, Prop. 2)."""
+    base = {n: B.colmajor(W.hermitian_kernel(n, seed=seed + i) if herm
+                          else W.similarity_kernel(n, seed=seed + i)[0], device=DEV)
             for i, n in enumerate(SIZES)}
     Ks = [base[n] for n in NS]
     us = [torch.from_numpy(W.uniform_stream(n, seed=1000 * seed + i)).to(DEV) for i, n in enumerate(NS)]
@@ -38,9 +40,9 @@ def _problems(B, seed):
     return Ks, us, As, outs
 
 
-def _snapshot(As, outs):
+def _snapshot(As, outs, herm=True):
     # LDL^H writes the lower triangle of A only.
-    return [(torch.tril(A), o["mask"].clone(), o["pivots"].clone(), o["loglik"].clone(), o["info"].clone())
+    return [(torch.tril(A) if herm else A.clone(), o["mask"].clone(), o["pivots"].clone(), o["loglik"].clone(), o["info"].clone())
             for A, o in zip(As, outs)]
 
 
@@ -57,25 +59,28 @@ def _equal(a, b):
     return all(torch.equal(x, y) for s, t in zip(a, b) for x, y in zip(s, t))
 
 
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "split"])
-def test_helper_lanes_equal_single_calls_and_replay(B, prec):
+def test_helper_lanes_equal_single_calls_and_replay(B, prec, herm):
     """The 64-problem batch equals single calls (one problem per size), and a
     graph of it captured on another stream replays that result bit for bit,
     with eager calls in between."""
-    Ks, us, As, outs = _problems(B, seed=60)
-    ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, NS, prec), dtype=torch.uint8,
+    Ks, us, As, outs = _problems(B, seed=60, herm=herm)
+    ws = torch.empty(B.dpp_workspace_size_batched(herm, B.DPP_F64, NS, prec), dtype=torch.uint8,
                      device=DEV)
-    call = lambda: B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, outs=outs, Ks=Ks)
+    fb = B.dpp_sample_ldlh_batched if herm else B.dpp_sample_lu_batched
+    call = lambda: fb(As, us, prec=prec, ws=ws, outs=outs, Ks=Ks)
+    snap = lambda: _snapshot(As, outs, herm)
     call()
     torch.cuda.synchronize()
-    ref = _snapshot(As, outs)
+    ref = snap()
     for o in outs:
         assert int(o["info"].item()) == 0
     for i in range(len(SIZES)):
         A1 = torch.empty_like(Ks[i])
-        s = B.dpp_sample_ldlh_batched([A1], [us[i]], prec=prec, Ks=[Ks[i]])[0]
+        s = fb([A1], [us[i]], prec=prec, Ks=[Ks[i]])[0]
         torch.cuda.synchronize()
-        assert _equal(_snapshot([A1], [s]), ref[i:i + 1]), NS[i]
+        assert _equal(_snapshot([A1], [s], herm), ref[i:i + 1]), NS[i]
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -88,7 +93,7 @@ def test_helper_lanes_equal_single_calls_and_replay(B, prec):
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        assert _equal(_snapshot(As, outs), ref), rep
+        assert _equal(snap(), ref), rep
         call()                                   # eager work between replays
         torch.cuda.synchronize()
 
