@@ -167,6 +167,16 @@ bool lanes_ready(Lanes& L, hipStream_t s)
         for (int i = 0; ok && i < kLanes - 1; ++i)
             ok = hipStreamCreateWithFlags(&L.hs[i], hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&L.join[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {  // release what was created; calls then use the caller's stream alone
+            for (int i = 0; i < kLanes - 1; ++i) {
+                if (L.hs[i]) (void)hipStreamDestroy(L.hs[i]);
+                if (L.join[i]) (void)hipEventDestroy(L.join[i]);
+                L.hs[i] = nullptr;
+                L.join[i] = nullptr;
+            }
+            if (L.fork) (void)hipEventDestroy(L.fork);
+            L.fork = nullptr;
+        }
         L.state = ok ? 1 : 2;
     }
     return L.state == 1;
