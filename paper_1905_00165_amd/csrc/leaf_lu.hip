@@ -31,7 +31,8 @@ using namespace leaf;
 // reads L11 by columns, the column panel U11^T, i.e. the same array by rows;
 // the odd pitch keeps both access patterns free of bank conflicts), and one
 // set of diagonal-block inverses, those of U11^T for the column panel, then
-// those of L11 for the row panel: 75 KiB, two workgroups per CU.
+// those of L11 for the row panel: 75 KiB, so two workgroups fit on a CU when
+// a launch needs more than one round.
 constexpr int kLP = L + 1;
 
 template <typename T, bool SPLIT>
@@ -278,6 +279,8 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
                     int64_t j0, int ss, hipStream_t s)
 {
     int gx = 1;
+    // Sized for one workgroup per CU: sizing for two (half the row groups per
+    // wavefront, twice the redundant chains) measured slower.
     const int gpw = groups_per_wave(nmax - c0 - L, nprob, 1, &gx);
     dim3 grid(gx, nprob), block(kThreads);
     if (split) hipLaunchKernelGGL((leaf_lu<T, true>), grid, block, 0, s, probs, c0, j0, ss, gpw);
