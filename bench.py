@@ -268,6 +268,21 @@ def graph_time(torch, step, reps, warmup=1):
     return e0.elapsed_time(e1) / reps
 
 
+def eager_time(torch, step, reps):
+    """Milliseconds per eager call over `reps` back-to-back calls (after one
+    warm-up), timed with events on the current stream: host enqueue time is
+    included wherever it exceeds the GPU's."""
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def bench_plain(torch, B, W, dev, cpu):
     """One sample of a dense Hermitian K, n = 1024 (FP64 storage), both paths:
     latency per sample (one out-of-place call, graph replay); with `cpu`, the oracle's
@@ -416,8 +431,12 @@ def bench_lensemble(torch, B, W, dev, count=4096):
             B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, outs=outs, Ks=Ks)
 
         ms = graph_time(torch, step, reps=3)
+        # The same call launched eagerly: host work (the binding's marshalling
+        # of 4096 problem descriptors, then the enqueue) sets the pace here.
+        ms_eager = eager_time(torch, step, reps=3)
         sizes = np.array([int(x) for x in torch.stack([o["mask"].sum() for o in outs]).cpu()])
         out[name] = {"ms_per_call": round(ms, 3), "samples_per_s": round(count / (ms * 1e-3), 1),
+                     "eager_ms_per_call": round(ms_eager, 3),
                      "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
                      "info_all_zero": bool((infos == 0).all().item()),
                      "max_size": int(sizes.max()), "size_le_rank": bool((sizes <= 64).all()),

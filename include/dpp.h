@@ -151,15 +151,7 @@ typedef struct {
  * problems, each with its own n, lda, stream of uniforms and outputs, sampled
  * by one launch sequence on `stream`: the problems are sorted by size into
  * groups, and each step of a group's factorization is one launch covering
- * every problem of the group that still has that step. A call of at least 64
- * problems in several groups spreads the groups over `stream` and two helper
- * streams that the library keeps per device (non-blocking, default priority,
- * created by the first such call on the device that is not under graph
- * capture; until then such calls run on `stream` alone): the helpers wait on
- * an event recorded on `stream` at the start, and `stream` waits on each of
- * them at the end, so the call is still ordered on `stream` as a whole and
- * captures as a fork/join. Calls on one device from several host threads
- * take turns while they enqueue such a call.
+ * every problem of the group that still has that step.
  *   probs   HOST array of `count` descriptors; it is read before the call
  *           returns and may be reused at once.
  *   ws      device workspace of dpp_workspace_size_batched(...) bytes.

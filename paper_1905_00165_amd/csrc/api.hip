@@ -26,7 +26,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -111,75 +110,6 @@ dpp_status device_ok()
         state[dev] = (strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 2;
     }
     return state[dev] == 1 ? DPP_OK : DPP_ERR_UNSUPPORTED;
-}
-
-// -------------------------------------------------------------- helper lanes
-// The size groups of a batch (below) share nothing but the read-only
-// descriptors: each problem has its own workspace. A call with several groups
-// spreads them over the caller's stream and kLanes - 1 helper streams of the
-// library, forked from the caller's stream (an event recorded on it) and joined
-// back to it before the call returns, so the call stays one stream-ordered unit
-// for the caller and a fork/join inside a captured graph. Small groups then
-// fill the machine while a large group waits on its diagonal-block chains.
-// Only calls of at least kLaneMinProblems problems fork: a caller that already
-// runs small batches on several streams of its own gains nothing from more
-// streams (they share a few hardware queues, where a waiting stream holds up
-// the others), and measured a loss.
-constexpr int kLanes = 3;
-constexpr int64_t kLaneMinProblems = 64;
-
-struct Lanes {
-    std::mutex mu;        // held while a call enqueues: the events are reused
-    int state = 0;        // 0 not created, 1 ready, 2 creation failed
-    hipStream_t hs[kLanes - 1] = {};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[kLanes - 1] = {};
-};
-
-// The lanes of the current device, or null when the caller's stream belongs to
-// another device (such a call runs its groups on the caller's stream alone).
-Lanes* lanes_of(hipStream_t s)
-{
-    static std::mutex mu;
-    static std::vector<std::unique_ptr<Lanes>> per_dev;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    if (s) {
-        hipDevice_t sd = -1;
-        if (hipStreamGetDevice(s, &sd) != hipSuccess || sd != dev) return nullptr;
-    }
-    std::lock_guard<std::mutex> g(mu);
-    if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1);
-    if (!per_dev[dev]) per_dev[dev].reset(new Lanes);
-    return per_dev[dev].get();
-}
-
-// Creates the helper streams (non-blocking, default priority) and events on
-// first use; never while the caller's stream is being captured, where creating
-// them is not allowed (that call then runs its groups on the caller's stream).
-bool lanes_ready(Lanes& L, hipStream_t s)
-{
-    if (L.state == 0) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-            return false;
-        bool ok = hipEventCreateWithFlags(&L.fork, hipEventDisableTiming) == hipSuccess;
-        for (int i = 0; ok && i < kLanes - 1; ++i)
-            ok = hipStreamCreateWithFlags(&L.hs[i], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&L.join[i], hipEventDisableTiming) == hipSuccess;
-        if (!ok) {  // release what was created; calls then use the caller's stream alone
-            for (int i = 0; i < kLanes - 1; ++i) {
-                if (L.hs[i]) (void)hipStreamDestroy(L.hs[i]);
-                if (L.join[i]) (void)hipEventDestroy(L.join[i]);
-                L.hs[i] = nullptr;
-                L.join[i] = nullptr;
-            }
-            if (L.fork) (void)hipEventDestroy(L.fork);
-            L.fork = nullptr;
-        }
-        L.state = ok ? 1 : 2;
-    }
-    return L.state == 1;
 }
 
 // ------------------------------------------------------------------ profiling
@@ -473,69 +403,19 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         if (st != DPP_OK) return st;
     }
 
-    struct Group {
-        int64_t p0, p1;
-        double cost;  // sum of n^3 (the update work)
-        int lane;
-    };
-    std::vector<Group> groups;
     for (int64_t p0 = 0; p0 < count;) {
         int64_t p1 = p0 + 1;
         while (p1 < count && size_group(host[(size_t)p1].n) == size_group(host[(size_t)p0].n)) ++p1;
-        double cost = 0.0;
-        for (int64_t p = p0; p < p1; ++p) cost += (double)host[(size_t)p].n * host[(size_t)p].n * host[(size_t)p].n;
-        groups.push_back(Group{p0, p1, cost, 0});
+        std::vector<int64_t> ns(ns_all.begin() + p0, ns_all.begin() + p1);
+        int64_t pmax = 0;
+        for (int64_t p = p0; p < p1; ++p) pmax = std::max(pmax, host[(size_t)p].npiv);
+        const Ctx g{plan, c.probs + p0, (int)(p1 - p0), host[(size_t)(p1 - 1)].n, pmax, s, &ns,
+                    profiling};
+        const dpp_status st = run_group(g);
+        if (st != DPP_OK) return st;
         p0 = p1;
     }
-
-    // Lanes: the heaviest groups first, each to the least loaded lane (ties to
-    // the lower lane). Which stream runs a group changes no result.
-    Lanes* L = groups.size() > 1 && count >= kLaneMinProblems ? lanes_of(s) : nullptr;
-    std::unique_lock<std::mutex> hold;
-    if (L) {
-        hold = std::unique_lock<std::mutex>(L->mu);
-        if (!lanes_ready(*L, s)) {
-            hold.unlock();
-            L = nullptr;
-        }
-    }
-    int nlanes = 1;
-    if (L) {
-        std::vector<size_t> by_cost(groups.size());
-        for (size_t i = 0; i < groups.size(); ++i) by_cost[i] = i;
-        std::stable_sort(by_cost.begin(), by_cost.end(),
-                         [&](size_t a, size_t b) { return groups[a].cost > groups[b].cost; });
-        double load[kLanes] = {};
-        for (size_t i : by_cost) {
-            int best = 0;
-            for (int l = 1; l < kLanes; ++l)
-                if (load[l] < load[best]) best = l;
-            groups[i].lane = best;
-            load[best] += groups[i].cost;
-            nlanes = std::max(nlanes, best + 1);
-        }
-        if (hipEventRecord(L->fork, s) != hipSuccess) return DPP_ERR_HIP;
-        for (int l = 1; l < nlanes; ++l)
-            if (hipStreamWaitEvent(L->hs[l - 1], L->fork, 0) != hipSuccess) return DPP_ERR_HIP;
-    }
-
-    dpp_status st = DPP_OK;
-    for (const Group& gr : groups) {
-        std::vector<int64_t> ns(ns_all.begin() + gr.p0, ns_all.begin() + gr.p1);
-        int64_t pmax = 0;
-        for (int64_t p = gr.p0; p < gr.p1; ++p) pmax = std::max(pmax, host[(size_t)p].npiv);
-        const hipStream_t gs = gr.lane == 0 ? s : L->hs[gr.lane - 1];
-        const Ctx g{plan, c.probs + gr.p0, (int)(gr.p1 - gr.p0), host[(size_t)(gr.p1 - 1)].n, pmax,
-                    gs, &ns, profiling};
-        st = run_group(g);
-        if (st != DPP_OK) break;
-    }
-    // Join every forked lane back to the caller's stream, also after an error.
-    for (int l = 1; l < nlanes; ++l)
-        if (hipEventRecord(L->join[l - 1], L->hs[l - 1]) != hipSuccess ||
-            hipStreamWaitEvent(s, L->join[l - 1], 0) != hipSuccess)
-            st = DPP_ERR_HIP;
-    return st;
+    return DPP_OK;
 }
 
 size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t count,

@@ -1,8 +1,6 @@
-"""Batched calls of at least 64 problems in several size groups run the groups
-on the caller's stream and on helper streams forked from it and joined back.
-These tests check that this changes no result: against single calls, under
-graph capture and replay, and with two callers' streams running such batches
-at the same time."""
+"""Batched calls of 64 problems in several size groups: each problem equals its
+single call, a captured call replays the eager result, and two callers'
+streams running such batches at the same time give what each gives alone."""
 import pytest
 
 from paper_1905_00165_amd import workloads as W
@@ -61,7 +59,7 @@ def _equal(a, b):
 
 @pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "split"])
-def test_helper_lanes_equal_single_calls_and_replay(B, prec, herm):
+def test_batch_of_64_equals_single_calls_and_replay(B, prec, herm):
     """The 64-problem batch equals single calls (one problem per size), and a
     graph of it captured on another stream replays that result bit for bit,
     with eager calls in between."""
