@@ -4,7 +4,7 @@
 // Launch sequence (blocked right-looking sampler, Sec. 3; the unblocked
 // sampler of Sec. 2 on each 64-wide diagonal block):
 //
-//   LDL^H, outer block width B0 (FP64: 1024, split-BF16: 4096):
+//   LDL^H, outer block width B0 (FP64: 2048, split-BF16: 4096):
 //     for each outer panel [j0, j1 = j0 + B0):
 //       factor_panel(j0, B0)                       -- recursive, below
 //       update rows/cols [j1, n) by columns [j0, j1) -- the trailing update
@@ -57,7 +57,7 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     // LU's rank-64 steps inside a panel touch ~ (n - j0) B0 / 2 entries of the
     // panel and ~ (n - j1) B0 / 2 of the rows of U to its right, against
     // (n - j1)^2 per trailing update; B0 = 512 balances them at n = 8192.
-    if (herm) p.B0 = p.split ? 4096 : 1024;
+    if (herm) p.B0 = p.split ? 4096 : 2048;
     else p.B0 = 512;
     // The split copies hold the columns of one outer panel, at most B0 and no
     // more than the largest problem has (rounded to whole blocks), so small
