@@ -133,6 +133,17 @@ def test_fp32_storage_split():
 
 
 @pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_fp32_storage_lu(prec):
+    """LU on an FP32-stored non-symmetric kernel (a diagonal similarity, n =
+    700: ten full blocks and a ragged one) against the oracle on the same
+    FP32 values widened to FP64."""
+    K, _ = W.similarity_kernel(700, seed=6)
+    u = W.uniform_stream(700, seed=6000)
+    tol, thr = (1e-5, 1e-6) if prec == 0 else (1e-4, 1e-5)
+    _check(False, K, u, prec, tol=tol, thr=thr, dtype=torch.float32)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
 def test_factor_reconstructs_k_minus_indicator(prec):
     n = 500
     K = W.hermitian_kernel(n, seed=6)
