@@ -1,13 +1,15 @@
 """Benchmark of the MI355X DPP sampler on the projection-kernel workload.
 
 Workload: K = Q_r Q_r^T, Q_r the Q factor of QR of a seeded N(0,1) n x r matrix
-(n = 16384, r = 4096), FP64 storage; every sample has its own seeded uniform
-stream and must have |Y| = r. A step samples `batch` independent samples of K
-in one batched LDL^H call (dpp_sample_ldlh_batched) that reads the resident K
-and writes each sample's factor to a buffer of its own (out of place: no
-per-sample copy of K). The headline
-`value` is the split-BF16 path's samples/s over the timed steps; the plain FP64
-path is timed the same way and reported beside it.
+(n = 16384, r = 4096), FP64 storage; 64 samples, each with its own seeded
+uniform stream (2000 .. 2063), every one of which must have |Y| = r. A step
+samples all 64: `calls` batched LDL^H calls (dpp_sample_ldlh_batched) of
+`batch` samples each, every call reading the resident K and writing each
+sample's factor to a buffer of its own (out of place: no per-sample copy of K).
+The headline `value` is the split-BF16 path's samples/s over the timed steps;
+the plain FP64 path is timed the same way and reported beside it. The CPU
+oracle samples stream 2000 in full on the host cores; that run is both the
+CPU baseline and the full-length error of both GPU paths on that stream.
 
 Throughput convention: TFLOP/s counts n^3/3 flops per LDL^H sample.
 
@@ -41,18 +43,18 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=16384)
     p.add_argument("--rank", type=int, default=4096)
-    p.add_argument("--batch", type=int, default=8)
+    p.add_argument("--batch", type=int, default=8, help="samples per batched call")
+    p.add_argument("--calls", type=int, default=8,
+                   help="batched calls per step (each on its own streams of uniforms)")
     p.add_argument("--prec", choices=["both", "split", "fp64"], default="both")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
-                   help="target length of the CPU oracle baseline sample (0: skip)")
+                   help="target CPU time of the oracle baselines of the extra workloads; "
+                        "0 skips every oracle run, including the whole n = 16384 sample")
     p.add_argument("--k-cache", default=None,
                    help="npy file holding K: loaded if present, else written after generation "
                         "(lets profiled runs skip the QR of the generator)")
     p.add_argument("--prepare-only", action="store_true",
                    help="generate (and cache) K, then exit")
-    p.add_argument("--streams", type=int, default=1,
-                   help="split each step's samples over this many concurrent batched calls, "
-                        "one per stream (forked and joined inside the step)")
     p.add_argument("--no-graph", action="store_true",
                    help="launch every step eagerly instead of replaying a captured HIP graph")
     p.add_argument("--copy-probe", action="store_true",
@@ -68,18 +70,21 @@ def parse():
 def run_path(torch, B, K, us, prec, args, As, ws):
     """Warm up, then time `args.steps` steps; returns timing and profile.
 
-    A step runs one batched call (or, with --streams S, S concurrent batched
-    calls over the samples, one per stream) that reads K in place of a working
-    copy and writes each sample's factor to its own buffer. By default one step is captured in a HIP graph and the timed steps
-    replay it (the launch list of a call depends only on the sizes, so every
-    replay does the full work on the same buffers); the per-kernel event
-    profile then comes from one eager step after the timed region."""
+    A step runs `args.calls` batched calls of `args.batch` samples (each
+    sample with its own stream, 64 in all by default); each call reads K in
+    place of a working copy and writes each sample's factor to a buffer of
+    its own (the buffers are reused by the next call of the step, the outputs
+    are not). By default one step is captured in a HIP graph and the timed
+    steps replay it (the launch list of a call depends only on the sizes, so
+    every replay does the full work on the same buffers); the per-kernel event
+    profile then comes from one eager call after the timed region."""
     n = K.shape[0]
     dev = K.device
     outs = [{"mask": torch.empty(n, dtype=torch.uint8, device=dev),
              "pivots": torch.empty(n, dtype=torch.float64, device=dev),
              "loglik": torch.empty(1, dtype=torch.float64, device=dev),
-             "info": torch.empty(1, dtype=torch.int32, device=dev)} for _ in As]
+             "info": torch.empty(1, dtype=torch.int32, device=dev),
+             "stats": torch.empty(3, dtype=torch.float64, device=dev)} for _ in us]
 
     Kc = K.t()  # column-major view (K is symmetric)
     if args.copy_probe:
@@ -87,28 +92,16 @@ def run_path(torch, B, K, us, prec, args, As, ws):
         B.dpp_copy_lower(scratch.t(), Kc)
         torch.cuda.synchronize()
         del scratch
-    S = max(1, min(args.streams, len(As)))
-    groups = [list(range(g, len(As), S)) for g in range(S)]
-    streams = [torch.cuda.Stream() for _ in range(S)] if S > 1 else []
-    wss = [ws] if S == 1 else [
-        torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, [n] * len(g), prec),
-                    dtype=torch.uint8, device=dev) for g in groups]
+    bsz = len(As)
 
-    def call(g, w):
-        B.dpp_sample_ldlh_batched([As[i].t() for i in g], [us[i] for i in g], prec=prec, ws=w,
-                                  outs=[outs[i] for i in g], Ks=[Kc] * len(g))
+    def call(c):
+        sl = slice(c * bsz, (c + 1) * bsz)
+        B.dpp_sample_ldlh_batched([A.t() for A in As], us[sl], prec=prec, ws=ws,
+                                  outs=outs[sl], Ks=[Kc] * bsz)
 
     def step():
-        if S == 1:
-            call(groups[0], wss[0])
-            return
-        main = torch.cuda.current_stream()
-        for st, g, w in zip(streams, groups, wss):
-            st.wait_stream(main)
-            with torch.cuda.stream(st):
-                call(g, w)
-        for st in streams:
-            main.wait_stream(st)
+        for c in range(args.calls):
+            call(c)
 
     for _ in range(args.warmup):
         step()
@@ -141,27 +134,27 @@ def run_path(torch, B, K, us, prec, args, As, ws):
     t1 = time.perf_counter()
     sizes = [int(o["mask"].sum().item()) for o in outs]
     infos = [int(o["info"].item()) for o in outs]
-    # Diagnostics of the decisions: the smallest |u_j - d_j| over the samples
-    # (how close any decision came to a tie) and the count of pre-decision
-    # probabilities outside [-1e-12, 1 + 1e-12] (rounding past [0, 1]).
-    margin, out_of_range = float("inf"), 0
-    for o, u in zip(outs, us):
-        d = o["pivots"] + 1.0 - o["mask"].to(torch.float64)
-        margin = min(margin, float(torch.min(torch.abs(u[:n] - d)).item()))
-        out_of_range += int(((d < -1e-12) | (d > 1.0 + 1e-12)).sum().item())
+    # The library's diagnostics of the decisions: the smallest |u_j - d_j| over
+    # the samples (how close any decision came to a tie), the count of
+    # pre-decision probabilities outside [-1e-12, 1 + 1e-12] (rounding past
+    # [0, 1]) and the largest distance of one from [0, 1].
+    st = torch.stack([o["stats"] for o in outs]).cpu().numpy()
+    margin, out_of_range, worst_out = float(st[:, 0].min()), int(st[:, 1].sum()), float(st[:, 2].max())
+    first = {k: outs[0][k].cpu().numpy() for k in ("mask", "pivots")}
+    first["loglik"] = float(outs[0]["loglik"].item())
     if graph is not None:
         B.dpp_profile_begin()
-        step()
+        call(0)
         prof = B.dpp_profile_end()
-        prof_samples = len(As)
-        sizes += [int(o["mask"].sum().item()) for o in outs]
-        infos += [int(o["info"].item()) for o in outs]
+        prof_samples = bsz
+        sizes += [int(o["mask"].sum().item()) for o in outs[:bsz]]
+        infos += [int(o["info"].item()) for o in outs[:bsz]]
         del graph
     else:
         prof = B.dpp_profile_end()
-        prof_samples = args.steps * len(As)
+        prof_samples = args.steps * len(us)
     wall_ms = (t1 - t0) * 1e3
-    samples = args.steps * len(As)
+    samples = args.steps * len(us)
     lib_ms = sum(v["ms"] for v in prof.values())
     flops_per_sample = n ** 3 / 3.0
     return {
@@ -170,8 +163,8 @@ def run_path(torch, B, K, us, prec, args, As, ws):
         "tflops": samples * flops_per_sample / (wall_ms * 1e-3) / 1e12,
         "kernel_ms_per_sample": lib_ms / prof_samples,
         "sizes": sizes, "infos": infos, "profile": prof,
-        "min_margin": margin, "d_out_of_range": out_of_range,
-        "event_ms": ev0.elapsed_time(ev1),
+        "min_margin": margin, "d_out_of_range": out_of_range, "d_worst_out": worst_out,
+        "event_ms": ev0.elapsed_time(ev1), "first": first,
     }
 
 
@@ -209,23 +202,16 @@ def roofline_entry(prof, name, peak):
             "hbm_gbs_algorithmic": round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 1)}
 
 
-def cpu_baseline(K_host, u0, n, seconds):
-    """The FP64 oracle on the first p pivots of one sample of the same K,
-    scaled by the fraction of the sampler's n^3/3 work those pivots do."""
+def cpu_baseline(K_host, u0, n):
+    """One whole sample of the same K (stream 2000) by the FP64 oracle on the
+    host cores; returns the baseline entry and the oracle's result."""
     import oracle
     threads = oracle.omp_threads()
     A = np.array(K_host.T, order="F", copy=True)   # column-major view of symmetric K
     t0 = time.perf_counter()
-    oracle.ldlh(A, u0, npiv=2, inplace=True)
-    t_probe = time.perf_counter() - t0
-    p = int(max(2, min(n, seconds / max(t_probe / 2, 1e-6))))
-    A = np.array(K_host.T, order="F", copy=True)
-    t0 = time.perf_counter()
-    oracle.ldlh(A, u0, npiv=p, inplace=True)
+    ref = oracle.ldlh(A, u0, inplace=True)
     t = time.perf_counter() - t0
-    j = np.arange(n, dtype=np.float64)
-    frac = float(np.sum((n - j[:p]) ** 2) / np.sum((n - j) ** 2))
-    sps = frac / t
+    del A
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -234,11 +220,30 @@ def cpu_baseline(K_host, u0, n, seconds):
                 break
     except OSError:
         pass
-    return {"value": sps, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "cpu_model": model, "affinity_cpus": len(os.sched_getaffinity(0)),
-            "sample": f"first {p} of {n} pivots of one sample (unblocked FP64 LDL^H, "
-                      f"{frac * 100:.3f}% of the n^3/3 work) in {t:.1f} s, scaled by that fraction",
-            "gflops": sps * n ** 3 / 3.0 / 1e9}
+    entry = {"value": 1.0 / t, "unit": "samples/s", "cores": threads, "kind": "oracle",
+             "cpu_model": model, "affinity_cpus": len(os.sched_getaffinity(0)),
+             "sample": f"one whole sample (stream 2000, all {n} pivots, unblocked FP64 LDL^H) "
+                       f"in {t:.1f} s",
+             "gflops": n ** 3 / 3.0 / t / 1e9}
+    return entry, {k: ref[k] for k in ("mask", "predec", "loglik", "info")}
+
+
+def parity_entry(first, ref, u, tol, thr):
+    """Full-length comparison of one GPU sample with the oracle's run on the
+    same bytes and stream (the near-tie rule: masks identical, or first
+    differing at an index where |u - d_oracle| < thr)."""
+    mask, piv, ll = first["mask"], first["pivots"], first["loglik"]
+    d_g = np.where(mask == 1, piv, piv + 1.0)
+    diff = np.nonzero(mask != ref["mask"])[0]
+    k = int(diff[0]) if diff.size else -1
+    upto = k + 1 if k >= 0 else len(mask)
+    dd = float(np.max(np.abs(d_g[:upto] - ref["predec"][:upto])))
+    tie = k >= 0 and abs(u[k] - ref["predec"][k]) < thr
+    ll_rel = abs(ll - ref["loglik"]) / abs(ref["loglik"]) if k < 0 else None
+    ok = (k < 0 or tie) and dd <= tol and (ll_rel is None or ll_rel <= tol)
+    return {"stream": 2000, "pivots_compared": upto, "first_mask_diff": k, "near_tie": bool(tie),
+            "max_abs_d_minus_oracle": dd, "loglik_rel_err": ll_rel, "tol": tol,
+            "near_tie_threshold": thr, "ok": bool(ok)}
 
 
 def graph_time(torch, step, reps, warmup=1):
@@ -568,7 +573,8 @@ def main():
             np.save(args.k_cache, K.cpu().numpy())
     if args.prepare_only:
         return
-    us = [torch.from_numpy(W.uniform_stream(n, seed=2000 + i)).to(dev) for i in range(bsz)]
+    nsamp = bsz * args.calls
+    us = [torch.from_numpy(W.uniform_stream(n, seed=2000 + i)).to(dev) for i in range(nsamp)]
     As = [torch.empty_like(K) for _ in range(bsz)]
     torch.cuda.synchronize()
 
@@ -578,7 +584,8 @@ def main():
     for name in order:
         ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, [n] * bsz, precs[name]),
                          dtype=torch.uint8, device=dev)
-        log(f"[bench] {name}: warmup {args.warmup}, steps {args.steps}, batch {bsz}")
+        log(f"[bench] {name}: warmup {args.warmup}, steps {args.steps}, {args.calls} calls "
+            f"of {bsz} samples per step")
         res[name] = run_path(torch, B, K, us, precs[name], args, As, ws)
         log(f"[bench] {name}: {res[name]['samples_per_s']:.2f} samples/s, "
             f"{res[name]['tflops']:.2f} TFLOP/s, sizes {set(res[name]['sizes'])}")
@@ -595,9 +602,11 @@ def main():
         "dtype": "bf16" if order[0] == "split" else "f64",
         "data": "synthetic",
         "config": {"workload": f"projection kernel K = Q_r Q_r^T, n={n}, rank={r}, FP64 storage; "
-                               f"LDL^H sampler, {bsz} samples per step (one batched call reading the "
-                               f"resident K out of place, each sample's factor to its own buffer)",
-                   "n": n, "rank": r, "batch": bsz,
+                               f"LDL^H sampler, {nsamp} samples per step on streams 2000-{1999 + nsamp} "
+                               f"({args.calls} batched calls of {bsz}, each reading the resident K out "
+                               f"of place and writing each sample's factor to its own buffer)",
+                   "n": n, "rank": r, "samples_per_step": nsamp, "batch": bsz,
+                   "calls": args.calls,
                    "precision": "split_bf16x3" if order[0] == "split" else "fp64",
                    "launch": "eager" if args.no_graph else "HIP graph replay of one step"},
         "tflops": round(head["tflops"], 3),
@@ -614,6 +623,7 @@ def main():
                      "info_all_zero": all(i == 0 for i in h["infos"]),
                      "min_abs_u_minus_d": h["min_margin"],
                      "pre_decision_d_outside_0_1": h["d_out_of_range"],
+                     "pre_decision_d_worst_outside": h["d_worst_out"],
                      "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
                                  for k, v in h["profile"].items()}}
     if "split" in res and "fp64" in res:
@@ -648,12 +658,17 @@ def main():
                                  "hbm_frac_of_peak": round(lf["bytes"] / (lf["ms"] * 1e-3) / PEAK_HBM, 4)}
 
     if args.cpu_seconds > 0:
-        log("[bench] CPU oracle baseline")
+        log("[bench] CPU oracle: one whole sample (stream 2000)")
         K_host = K.cpu().numpy()
         del As, K
         torch.cuda.empty_cache()
-        out["cpu_baseline"] = cpu_baseline(K_host, W.uniform_stream(n, seed=2000), n,
-                                           args.cpu_seconds)
+        u0 = W.uniform_stream(n, seed=2000)
+        out["cpu_baseline"], ref = cpu_baseline(K_host, u0, n)
+        del K_host
+        tols = {"split": (1e-4, 1e-5), "fp64": (1e-9, 1e-10)}
+        for name in order:
+            out[name]["vs_oracle"] = parity_entry(res[name]["first"], ref, u0, *tols[name])
+            log(f"[bench] {name} vs oracle: {out[name]['vs_oracle']}")
     else:
         out["cpu_baseline"] = None
     if args.extra:

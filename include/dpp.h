@@ -16,7 +16,9 @@
  *   - Every pointer argument except `probs` of the batched calls and the
  *     return-value strings is a DEVICE pointer owned by the caller. The library
  *     allocates no memory: all scratch space comes from the caller's workspace
- *     `ws` of `ws_bytes` bytes (query the size with dpp_workspace_size*).
+ *     `ws` of `ws_bytes` bytes (query the size with dpp_workspace_size*),
+ *     which must be 256-byte aligned (DPP_ERR_INVALID_ARG otherwise; device
+ *     allocations are). Its contents on entry are ignored.
  *   - Matrices are column-major with leading dimension max(1, n) <= lda <=
  *     2^20 (the kernels address strips of up to 256 columns with 32-bit
  *     byte offsets).
@@ -131,7 +133,16 @@ size_t dpp_workspace_size(int hermitian, dpp_dtype dt, int64_t n, dpp_precision 
              remaining indices conditioned on those decisions: the Schur
              complement of K - 1_{Y^c} restricted to the decided indices
              (Props. 3-5). Sampling that block with its own call continues the
-             same chain. Argument error otherwise. */
+             same chain. Argument error otherwise.
+     stats   out, optional (NULL: not computed), 3 FP64 diagnostics of the
+             decisions over the decided indices j, with d_j the pre-decision
+             probability (recovered as d'_j, or d'_j + 1 for a rejection):
+               stats[0] = min_j |u_j - d_j|, how close any decision came to a
+                          tie (the near-tie margin; +inf if no index decided);
+               stats[1] = the number of j with d_j < -1e-12 or d_j > 1 + 1e-12
+                          (probabilities pushed out of [0, 1] by rounding,
+                          compared as they are: no clamping);
+               stats[2] = max_j of the distance from d_j to [0, 1] (0 if none). */
 typedef struct {
     void* A;
     int64_t n;
@@ -144,6 +155,7 @@ typedef struct {
     const void* K;
     int64_t ldk;
     int64_t npiv;
+    double* stats;
 } dpp_problem;
 
 /*
@@ -183,7 +195,6 @@ size_t dpp_workspace_size_batched(int hermitian, dpp_dtype dt, const int64_t* ns
 dpp_status dpp_copy_lower(void* dst, const void* src, dpp_dtype dt, int64_t n, int64_t ld_dst,
                           int64_t ld_src, void* stream);
 
-/* Static, NUL-terminated description of a status code. */
 /*
  * dpp_lensemble_to_marginal_batched - on-device conversion of `count`
  * Hermitian (real symmetric) L-ensemble kernels into marginal kernels,
@@ -226,6 +237,7 @@ dpp_status dpp_lensemble_to_marginal_batched(const dpp_lensemble* probs, int64_t
    invalid arguments. */
 size_t dpp_lensemble_workspace_size(const int64_t* ns, int64_t count);
 
+/* Static, NUL-terminated description of a status code. */
 const char* dpp_status_string(dpp_status s);
 
 /*

@@ -32,7 +32,7 @@ class DppError(RuntimeError):
 class dpp_problem(ctypes.Structure):
     _fields_ = [("A", _vp), ("n", _i64), ("lda", _i64), ("u", _vp), ("mask", _vp),
                 ("pivots", _vp), ("loglik", _vp), ("info", _vp), ("K", _vp), ("ldk", _i64),
-                ("npiv", _i64)]
+                ("npiv", _i64), ("stats", _vp)]
 
 
 class dpp_lensemble(ctypes.Structure):
@@ -173,16 +173,61 @@ def _check_matrix(A):
     return n, lda
 
 
-def _outputs(n, device, out):
+# Output buffers of one problem: (dtype name, entries needed for n indices).
+_OUTPUTS = {"mask": ("uint8", lambda n: n), "pivots": ("float64", lambda n: n),
+            "loglik": ("float64", lambda n: 1), "info": ("int32", lambda n: 1),
+            "stats": ("float64", lambda n: 3)}
+
+
+def check_outputs(o, n, device):
+    """Every supplied output buffer must live on `device`, with the dtype and at
+    least the entries the library writes (a host tensor here would hand the
+    kernels a host pointer). Raises ValueError otherwise."""
     torch = _torch()
-    if out is None:
-        out = {}
-    o = dict(out)
+    for key, t in o.items():
+        if key not in _OUTPUTS:
+            raise ValueError(f"unknown output {key!r}")
+        dt, need = _OUTPUTS[key]
+        if t.device != device:
+            raise ValueError(f"output {key!r} is on {t.device}, the problem on {device}")
+        if t.dtype != getattr(torch, dt):
+            raise ValueError(f"output {key!r} must be {dt}, got {t.dtype}")
+        if t.numel() < need(n) or not t.is_contiguous():
+            raise ValueError(f"output {key!r} must be contiguous with >= {need(n)} entries")
+
+
+def check_stream(u, n, device):
+    """A uniform stream: contiguous float64 on `device` with >= n entries."""
+    torch = _torch()
+    if u.dtype != torch.float64 or u.device != device or u.numel() < n or not u.is_contiguous():
+        raise ValueError("u must be a contiguous float64 tensor on the problem's device "
+                         "with >= n entries")
+
+
+def _outputs(n, device, out, stats=True):
+    """The caller's output buffers (checked), the missing ones allocated. With
+    `stats`, a problem whose outputs are all allocated here also gets the
+    3-entry decision diagnostics buffer."""
+    torch = _torch()
+    o = dict(out) if out else {}
+    check_outputs(o, n, device)
     o.setdefault("mask", torch.empty(n, dtype=torch.uint8, device=device))
     o.setdefault("pivots", torch.empty(n, dtype=torch.float64, device=device))
     o.setdefault("loglik", torch.empty(1, dtype=torch.float64, device=device))
     o.setdefault("info", torch.empty(1, dtype=torch.int32, device=device))
+    if stats and not out:
+        o["stats"] = torch.empty(3, dtype=torch.float64, device=device)
     return o
+
+
+def _workspace(ws, need, device):
+    """The caller's workspace (a contiguous uint8 tensor on `device`), or a new one."""
+    torch = _torch()
+    if ws is None:
+        return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    if ws.device != device or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 tensor on the problem's device")
+    return ws
 
 
 def _stream_handle(device):
@@ -191,15 +236,13 @@ def _stream_handle(device):
 
 
 def _single(name, hermitian, A, u, prec, ws, out):
-    torch = _torch()
+    if out and "stats" in out:
+        raise ValueError("the single-problem calls have no stats output; use the batched form")
     n, lda = _check_matrix(A)
     dt = _dtype_code(A)
-    if u.dtype != torch.float64 or u.device != A.device or u.numel() < n or not u.is_contiguous():
-        raise ValueError("u must be a contiguous float64 device tensor with >= n entries")
-    need = dpp_workspace_size(hermitian, dt, n, prec)
-    if ws is None:
-        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
-    o = _outputs(n, A.device, out)
+    check_stream(u, n, A.device)
+    ws = _workspace(ws, dpp_workspace_size(hermitian, dt, n, prec), A.device)
+    o = _outputs(n, A.device, out, stats=False)
     st = getattr(lib(), name)(A.data_ptr(), dt, n, lda, u.data_ptr(), o["mask"].data_ptr(),
                               o["pivots"].data_ptr(), o["loglik"].data_ptr(),
                               o["info"].data_ptr(), int(prec), ws.data_ptr(), ws.numel(),
@@ -222,41 +265,42 @@ def dpp_sample_lu(A, u, prec=DPP_PREC_FP64, ws=None, out=None):
 
 
 def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None, npivs=None):
-    torch = _torch()
     if len(As) != len(us) or not As:
         raise ValueError("need matching, non-empty lists of matrices and streams")
     if Ks is not None and len(Ks) != len(As):
         raise ValueError("Ks needs one source matrix (or None) per problem")
     if npivs is not None and len(npivs) != len(As):
         raise ValueError("npivs needs one count (or 0 for all) per problem")
+    if outs is not None and len(outs) != len(As):
+        raise ValueError("outs needs one dict (or None) per problem")
     dt = _dtype_code(As[0])
+    dev = As[0].device
     probs = (dpp_problem * len(As))()
     res = []
     ns = []
     for i, (A, u) in enumerate(zip(As, us)):
         n, lda = _check_matrix(A)
-        if _dtype_code(A) != dt:
-            raise ValueError("all matrices of a batch share one dtype")
-        if u.dtype != torch.float64 or u.numel() < n or not u.is_contiguous():
-            raise ValueError("each u must be a contiguous float64 device tensor with >= n entries")
+        if _dtype_code(A) != dt or A.device != dev:
+            raise ValueError("all matrices of a batch share one dtype and one device")
+        check_stream(u, n, dev)
         kp, ldk = None, 0
         K = Ks[i] if Ks is not None else None
         if K is not None:
             nk, ldk = _check_matrix(K)
-            if nk != n or _dtype_code(K) != dt or K.device != A.device:
+            if nk != n or _dtype_code(K) != dt or K.device != dev:
                 raise ValueError("each K must match its A in size, dtype and device")
             kp = K.data_ptr()
-        o = _outputs(n, A.device, outs[i] if outs else None)
+        o = _outputs(n, dev, outs[i] if outs else None)
+        st = o.get("stats")
         probs[i] = dpp_problem(A.data_ptr(), n, lda, u.data_ptr(), o["mask"].data_ptr(),
                                o["pivots"].data_ptr(), o["loglik"].data_ptr(),
-                               o["info"].data_ptr(), kp, ldk, int(npivs[i]) if npivs else 0)
+                               o["info"].data_ptr(), kp, ldk, int(npivs[i]) if npivs else 0,
+                               st.data_ptr() if st is not None else None)
         res.append(o)
         ns.append(n)
-    need = dpp_workspace_size_batched(hermitian, dt, ns, prec)
-    if ws is None:
-        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=As[0].device)
+    ws = _workspace(ws, dpp_workspace_size_batched(hermitian, dt, ns, prec), dev)
     st = getattr(lib(), name)(probs, len(As), dt, int(prec), ws.data_ptr(), ws.numel(),
-                              _stream_handle(As[0].device))
+                              _stream_handle(dev))
     if st != DPP_OK:
         raise DppError(st, name)
     return res
@@ -297,10 +341,12 @@ def dpp_lensemble_to_marginal_batched(Ls, Ks=None, ws=None):
         n, ldl = _check_matrix(Lm)
         if _dtype_code(Lm) != dt:
             raise ValueError("all matrices of a batch share one dtype")
+        if Lm.device != Ls[0].device:
+            raise ValueError("all matrices of a batch live on one device")
         K = Ks[i] if Ks is not None and Ks[i] is not None else torch.empty_like(Lm)
         nk, ldk = _check_matrix(K)
-        if nk != n or _dtype_code(K) != dt:
-            raise ValueError("each K must match its L in size and dtype")
+        if nk != n or _dtype_code(K) != dt or K.device != Lm.device:
+            raise ValueError("each K must match its L in size, dtype and device")
         o = {"K": K, "logdet": torch.empty(1, dtype=torch.float64, device=Lm.device),
              "info": torch.empty(1, dtype=torch.int32, device=Lm.device)}
         probs[i] = dpp_lensemble(Lm.data_ptr(), n, ldl, K.data_ptr(), ldk,
@@ -309,8 +355,7 @@ def dpp_lensemble_to_marginal_batched(Ls, Ks=None, ws=None):
     need = dpp_lensemble_workspace_size([Lm.shape[0] for Lm in Ls])
     if need == 0:
         raise ValueError("sizes out of range for the conversion")
-    if ws is None:
-        ws = torch.empty(need, dtype=torch.uint8, device=Ls[0].device)
+    ws = _workspace(ws, need, Ls[0].device)
     st = lib().dpp_lensemble_to_marginal_batched(probs, len(Ls), dt, ws.data_ptr(), ws.numel(),
                                                  _stream_handle(Ls[0].device))
     if st != DPP_OK:

@@ -344,6 +344,10 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     size_t need = desc_bytes(count);
     for (int64_t i = 0; i < count; ++i) need += problem_bytes(plan, probs[i].n);
     if (!ws || ws_bytes < need) return DPP_ERR_WORKSPACE;
+    // The split planes take 16-byte stores and direct-to-LDS reads, the
+    // diagonal strip 8-byte accesses; every piece starts at a multiple of
+    // kAlign from ws.
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return DPP_ERR_INVALID_ARG;
     const dpp_status dev = device_ok();
     if (dev != DPP_OK) return dev;
 
@@ -379,6 +383,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.piv = q.pivots;
         d.loglik = q.loglik;
         d.info = q.info;
+        d.stats = q.stats;
         d.diag = reinterpret_cast<double*>(base_of[(size_t)i]);
         d.split = plan.split ? reinterpret_cast<uint16_t*>(base_of[(size_t)i] + diag_bytes(q.n))
                              : nullptr;
@@ -504,6 +509,7 @@ dpp_status dpp_lensemble_to_marginal_batched(const dpp_lensemble* probs, int64_t
     const size_t need = lens_workspace(ns.data(), count, &ms);
     if (need == 0) return DPP_ERR_INVALID_ARG;
     if (!ws || ws_bytes < need) return DPP_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return DPP_ERR_INVALID_ARG;
     const dpp_status dev = device_ok();
     if (dev != DPP_OK) return dev;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -540,7 +546,7 @@ dpp_status dpp_lensemble_to_marginal_batched(const dpp_lensemble* probs, int64_t
         d.info = q.info;
         mmax = std::max(mmax, m);
         fact[(size_t)i] = dpp_problem{d.aug, m, m, d.u, d.mask, piv, d.loglik, d.sinfo,
-                                      nullptr, 0, d.np};
+                                      nullptr, 0, d.np, nullptr};
     }
     dpp::LensDesc* ddesc = static_cast<dpp::LensDesc*>(ws);
     for (int64_t i = 0; i < count; i += dpp::kLensDescPerLaunch) {

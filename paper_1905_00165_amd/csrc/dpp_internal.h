@@ -27,6 +27,7 @@ struct DevProb {
     uint16_t* split;  // split-BF16 panel copies (see below), or nullptr
     double* diag;     // ceil(n/64) factored 64x64 diagonal blocks, column-major,
                       // block b at diag[b * 64 * 64]; copied into A at the end
+    double* stats;    // 3 decision diagnostics (finalize.hip), or nullptr
 };
 
 // Out-of-place calls put the factor in A and leave K untouched. Every entry

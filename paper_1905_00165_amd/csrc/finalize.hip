@@ -1,4 +1,4 @@
-// Log-likelihood and info word of each problem (gfx950).
+// Log-likelihood, info word and decision diagnostics of each problem (gfx950).
 //
 // The likelihood of the returned sample is the product of the absolute values
 // of the modified pivots (Theorem 2), so loglik = sum_j ln|d'_j| over the
@@ -6,12 +6,18 @@
 // in a fixed order (each thread sums a contiguous chunk in index order, then a
 // fixed binary tree), so the result is bitwise reproducible. info is the
 // 1-based index of the first pivot that is exactly zero or NaN (0 if none).
+//
+// Diagnostics (optional): with d_j the pre-decision probability (d'_j if kept,
+// d'_j + 1 if rejected, since a rejection subtracts 1, Prop. 4), the smallest
+// |u_j - d_j| (how near a decision came to a tie), the number of d_j outside
+// [-1e-12, 1 + 1e-12] and the largest distance of a d_j from [0, 1].
 #include "dpp_internal.h"
 
 namespace dpp {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr double kRangeSlack = 1e-12;
 
 __global__ __launch_bounds__(kThreads) void finalize(const DevProb* __restrict__ probs)
 {
@@ -21,28 +27,47 @@ __global__ __launch_bounds__(kThreads) void finalize(const DevProb* __restrict__
     const int64_t chunk = (n + kThreads - 1) / kThreads;
     const int64_t lo = tid * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    double s = 0.0;
+    const bool diag = P.stats != nullptr;
+    double s = 0.0, gap = INFINITY, far = 0.0, outside = 0.0;
     int64_t first = INT64_MAX;
     for (int64_t j = lo; j < hi; ++j) {
         const double p = P.piv[j];
         s += log(fabs(p));
         if (first == INT64_MAX && (p == 0.0 || p != p)) first = j;
+        if (diag) {
+            const double d = P.mask[j] ? p : p + 1.0;
+            gap = fmin(gap, fabs(P.u[j] - d));
+            const double dist = d < 0.0 ? -d : (d > 1.0 ? d - 1.0 : 0.0);
+            far = fmax(far, dist);
+            outside += (d < -kRangeSlack || d > 1.0 + kRangeSlack) ? 1.0 : 0.0;
+        }
     }
-    __shared__ double ss[kThreads];
+    __shared__ double ss[kThreads], sg[kThreads], sd[kThreads], so[kThreads];
     __shared__ int64_t sf[kThreads];
     ss[tid] = s;
     sf[tid] = first;
+    sg[tid] = gap;
+    sd[tid] = far;
+    so[tid] = outside;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
         if (tid < w) {
             ss[tid] = ss[tid] + ss[tid + w];
             sf[tid] = sf[tid] < sf[tid + w] ? sf[tid] : sf[tid + w];
+            sg[tid] = fmin(sg[tid], sg[tid + w]);
+            sd[tid] = fmax(sd[tid], sd[tid + w]);
+            so[tid] = so[tid] + so[tid + w];
         }
         __syncthreads();
     }
     if (tid == 0) {
         *P.loglik = ss[0];
         *P.info = sf[0] == INT64_MAX ? 0 : (int32_t)(sf[0] + 1);
+        if (diag) {
+            P.stats[0] = sg[0];
+            P.stats[1] = so[0];
+            P.stats[2] = sd[0];
+        }
     }
 }
 

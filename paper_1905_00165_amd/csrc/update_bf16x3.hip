@@ -93,21 +93,34 @@ __device__ __forceinline__ int swz(int r)
     return ROWB == 64 ? (r >> 2) & 3 : ((r >> 2) ^ (r >> 3)) & 1;
 }
 
-// s_waitcnt immediate that waits until at most n vector-memory loads of this
-// wavefront are outstanding (expcnt and lgkmcnt left alone).
-__device__ __forceinline__ void wait_vmcnt_le(int n)
+// s_waitcnt immediate that waits until at most N vector-memory loads of this
+// wavefront are outstanding (expcnt and lgkmcnt left at their maxima, i.e.
+// not waited on). gfx9 layout: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8.
+template <int N>
+constexpr int vmcnt_imm()
 {
-    switch (n) {
-    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-    case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
-    case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
-    case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
-    case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
-    case 16: __builtin_amdgcn_s_waitcnt(0x4F70); break;
-    case 24: __builtin_amdgcn_s_waitcnt(0x4F78); break;
-    case 32: __builtin_amdgcn_s_waitcnt(0x8F70); break;
-    default: __builtin_amdgcn_s_waitcnt(0x0F70); break;  // vmcnt(0): always safe
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit counter");
+    return (N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+}
+static_assert(vmcnt_imm<0>() == 0x0F70 && vmcnt_imm<6>() == 0x0F76 && vmcnt_imm<24>() == 0x4F78,
+              "s_waitcnt encoding");
+
+// Wait until at most (stages still in flight) * PER_WAVE loads are
+// outstanding; `later` is 0 .. NST - 2, the stages issued after this one.
+template <int NST, int PER_WAVE>
+__device__ __forceinline__ void wait_stages_le(int later)
+{
+    static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
+    if (NST >= 4 && later == 2) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NST >= 4 ? 2 : 0) * PER_WAVE>());
+        return;
     }
+    if (NST >= 3 && later == 1) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NST >= 3 ? 1 : 0) * PER_WAVE>());
+        return;
+    }
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
 }
 
 constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format, gfx9 resource word 3
@@ -358,7 +371,7 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
         // already issued may still be in flight); the barrier makes everyone's
         // visible and retires every read of the buffer refilled next.
         const int later = nstages - 1 - st < S::NST - 2 ? nstages - 1 - st : S::NST - 2;
-        wait_vmcnt_le(later * S::PER_WAVE);
+        wait_stages_le<S::NST, S::PER_WAVE>(later);
         // A bare s_barrier: __syncthreads() would add a release fence, i.e.
         // vmcnt(0), and drain the stages still in flight. Ordering needs no
         // fence here: each wavefront has waited for its own copies of this

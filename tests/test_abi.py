@@ -145,3 +145,54 @@ def test_partial_and_lensemble_argument_errors():
 def test_profile_without_launches_is_empty():
     B.dpp_profile_begin()
     assert B.dpp_profile_end() == {}
+
+
+def test_misaligned_workspace_is_refused():
+    """The workspace must be 256-byte aligned (the split planes take 16-byte
+    stores and direct-to-LDS reads); an offset into an arena is refused before
+    any launch."""
+    lib = B.lib()
+    p = 0x100000
+    probs = (B.dpp_problem * 1)(B.dpp_problem(p, 10, 10, p, p, p, p, p))
+    for off in (8, 16, 128):
+        assert lib.dpp_sample_ldlh_batched(probs, 1, 0, 0, ctypes.c_void_p(p + off), 1 << 40,
+                                           None) == 1
+        assert lib.dpp_sample_lu_batched(probs, 1, 0, 1, ctypes.c_void_p(p + off), 1 << 40,
+                                         None) == 1
+    f = lib.dpp_sample_ldlh
+    assert f(ctypes.c_void_p(p), 0, 10, 10, ctypes.c_void_p(p), ctypes.c_void_p(p),
+             ctypes.c_void_p(p), ctypes.c_void_p(p), ctypes.c_void_p(p), 0,
+             ctypes.c_void_p(p + 64), 1 << 40, None) == 1
+    q = (B.dpp_lensemble * 1)(B.dpp_lensemble(p, 10, 10, p, 10, None, p))
+    assert lib.dpp_lensemble_to_marginal_batched(q, 1, 0, ctypes.c_void_p(p + 8), 1 << 40,
+                                                 None) == 1
+
+
+def test_binding_checks_output_buffers_and_streams():
+    """Outputs and streams on the wrong device, of the wrong dtype or too short
+    are refused by the binding before the library sees a pointer (a host
+    buffer would otherwise reach the kernels)."""
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cpu")
+    ok = {"mask": torch.empty(5, dtype=torch.uint8), "pivots": torch.empty(5, dtype=torch.float64),
+          "loglik": torch.empty(1, dtype=torch.float64), "info": torch.empty(1, dtype=torch.int32),
+          "stats": torch.empty(3, dtype=torch.float64)}
+    B.check_outputs(ok, 5, dev)
+    bad = [("mask", torch.empty(5, dtype=torch.uint8, device="meta")),     # other device
+           ("pivots", torch.empty(5, dtype=torch.float32)),               # dtype
+           ("pivots", torch.empty(4, dtype=torch.float64)),               # too short
+           ("info", torch.empty(1, dtype=torch.int64)),
+           ("stats", torch.empty(2, dtype=torch.float64)),
+           ("mask", torch.empty(10, dtype=torch.uint8)[::2])]             # not contiguous
+    for key, t in bad:
+        o = dict(ok)
+        o[key] = t
+        with pytest.raises(ValueError):
+            B.check_outputs(o, 5, dev)
+    with pytest.raises(ValueError):
+        B.check_outputs({"extra": torch.empty(1)}, 5, dev)
+    B.check_stream(torch.empty(5, dtype=torch.float64), 5, dev)
+    for u in (torch.empty(5, dtype=torch.float64, device="meta"), torch.empty(5),
+              torch.empty(4, dtype=torch.float64), torch.empty(10, dtype=torch.float64)[::2]):
+        with pytest.raises(ValueError):
+            B.check_stream(u, 5, dev)

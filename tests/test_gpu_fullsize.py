@@ -1,21 +1,24 @@
 """GPU checks at the full benchmark size, in the benchmark's launch
 configuration: the projection kernel K = Q_r Q_r^T with n = 16384, rank 4096,
-eight samples per batched LDL^H call, FP64 storage, both precisions.
+FP64 storage, eight samples per batched LDL^H call reading the resident K out
+of place, both precisions.
 
-A full oracle run at this size takes many minutes, so the checks are properties
-that hold at any size, plus outputs the oracle (or the plain definition behind
-it) can compute one at a time:
-  - |Y| = rank for every sample (Sec. 1: projection kernels);
-  - the decision rule on the GPU's own probabilities: keep j iff u_j < d_j;
+  - full-length parity: samples on streams 2000 and 2001 against whole oracle
+    runs on the same bytes and streams (Sec. 2, Theorem 2 and the unblocked
+    listing; Sec. 3 blocked form with Prop. 5), every pivot and the
+    log-likelihood, under the near-tie rule of tests/parity.py;
+  - |Y| = rank for every sample of 64 distinct streams (Sec. 1: projection
+    kernels give samples of size exactly their rank);
+  - the decision rule on the GPU's own probabilities: keep j iff u_j < d_j,
+    and the library's decision diagnostics against a recomputation;
   - sampled entries of L D L^T equal K - 1_{Y^c} (the factor is the in-place
     LDL^H of K - 1_{Y^c});
-  - the first pivots equal a bounded oracle run (first p pivots, same stream);
-  - at sampled indices j, the GPU's d_j equals the conditional inclusion
-    probability given the GPU's own decisions for 0..j-1, computed from K by a
-    library solve (Props. 3-5) -- this bounds the accumulated error deep into
-    the factorization without needing the same trajectory as the oracle.
-Tolerances: FP64 1e-9; split-BF16 1e-4 (probabilities) and 1e-4 relative
-(factor entries, scaled by the magnitude of the entries involved).
+  - at sampled indices j in every outer panel, the GPU's d_j equals the
+    conditional inclusion probability given the GPU's own decisions for
+    0..j-1, computed from K by a library solve (Props. 3-5).
+Tolerances: FP64 1e-9 (near-tie threshold 1e-10); split-BF16 1e-4 (threshold
+1e-5), on probabilities, relative on the log-likelihood and on factor entries
+(scaled by the magnitude of the entries involved).
 """
 import numpy as np
 import pytest
@@ -30,6 +33,7 @@ pytestmark = pytest.mark.gpu
 N, RANK, BATCH = 16384, 4096, 8
 TOL = {0: 1e-9, 1: 1e-4}
 THR = {0: 1e-10, 1: 1e-5}
+NAME = {0: "fp64", 1: "split"}
 
 
 @pytest.fixture(scope="module")
@@ -38,6 +42,7 @@ def setup():
         pytest.skip("no GPU")
     from paper_1905_00165_amd import binding as B
     dev = torch.device("cuda:0")
+    print(f"[fullsize] generating K: n={N} rank={RANK}", flush=True)
     K = W.projection_kernel(N, RANK, seed=2, device=dev)
     torch.cuda.synchronize()
     Kh = K.cpu().numpy()
@@ -45,24 +50,62 @@ def setup():
     return B, dev, K, Kh, us
 
 
+def _call(B, K, uts, prec, As, outs=None):
+    """One batched out-of-place call, as the benchmark makes it."""
+    Kc = K.t()  # column-major view (K is symmetric)
+    return B.dpp_sample_ldlh_batched([A.t() for A in As], uts, prec=prec, Ks=[Kc] * len(As),
+                                     outs=outs)
+
+
 @pytest.fixture(scope="module", params=[0, 1], ids=["fp64", "split"])
 def run(request, setup):
     B, dev, K, Kh, us = setup
     prec = request.param
-    As = [K.clone() for _ in range(BATCH)]
+    print(f"[fullsize] {NAME[prec]}: {BATCH} samples, one batched call", flush=True)
+    As = [torch.empty_like(K) for _ in range(BATCH)]
     uts = [torch.from_numpy(u).to(dev) for u in us]
-    outs = B.dpp_sample_ldlh_batched([A.t() for A in As], uts, prec=prec)
+    outs = _call(B, K, uts, prec, As)
     torch.cuda.synchronize()
     res = []
     for i, (A, o) in enumerate(zip(As, outs)):
         res.append({"mask": o["mask"].cpu().numpy(), "pivots": o["pivots"].cpu().numpy(),
                     "loglik": float(o["loglik"].cpu()[0]), "info": int(o["info"].cpu()[0]),
+                    "stats": o["stats"].cpu().numpy(),
                     # factor of the first two samples, as a host copy of the
                     # column-major buffer (row-major view of its transpose)
                     "A": A.cpu() if i < 2 else None})
     del As, outs
     torch.cuda.empty_cache()
     return prec, res
+
+
+_ORACLE = {}
+
+
+def _oracle(Kh, us, i):
+    """A whole oracle run on stream 2000 + i (about a minute on 16 cores),
+    computed once per module."""
+    if i not in _ORACLE:
+        print(f"[fullsize] oracle run on stream {2000 + i}", flush=True)
+        A = np.array(Kh.T, order="F", copy=True)   # column-major copy of symmetric K
+        r = oracle.ldlh(A, us[i], inplace=True)
+        del A
+        _ORACLE[i] = {k: r[k] for k in ("mask", "predec", "loglik", "info")}
+    return _ORACLE[i]
+
+
+@pytest.mark.parametrize("i", [0, 1])
+def test_full_length_parity_with_oracle(run, setup, i):
+    prec, res = run
+    Kh, us = setup[3], setup[4]
+    ref = _oracle(Kh, us, i)
+    r = res[i]
+    assert ref["info"] == 0 and r["info"] == 0
+    v = compare(r["mask"], r["pivots"], r["loglik"], ref, us[i], TOL[prec], THR[prec])
+    print(f"[accuracy] prec={NAME[prec]} stream {2000 + i}, all {N} pivots: first mask diff "
+          f"{v.first_diff}, near tie {v.near_tie}, max |d_gpu - d_oracle| = {v.max_dd:.3e}, "
+          f"|dll|/|ll| = {v.ll_rel:.3e}, min |u - d| = {v.min_gap:.3e}")
+    assert v.ok, v.why
 
 
 def test_sample_size_and_info(run):
@@ -72,14 +115,48 @@ def test_sample_size_and_info(run):
         assert int(r["mask"].sum()) == RANK
 
 
-def test_decision_rule_on_own_probabilities(run, setup):
+def test_rank_invariant_on_64_streams(setup):
+    """Each of 64 samples on its own stream (2000-2063), eight batched calls
+    of eight, both precisions: |Y| = 4096 exactly and info = 0."""
+    B, dev, K = setup[0], setup[1], setup[2]
+    As = [torch.empty_like(K) for _ in range(BATCH)]
+    for prec in (0, 1):
+        sizes, infos = [], []
+        for c in range(64 // BATCH):
+            uts = [torch.from_numpy(W.uniform_stream(N, seed=2000 + BATCH * c + i)).to(dev)
+                   for i in range(BATCH)]
+            outs = _call(B, K, uts, prec, As)
+            torch.cuda.synchronize()
+            sizes += [int(o["mask"].sum().item()) for o in outs]
+            infos += [int(o["info"].item()) for o in outs]
+        assert sizes == [RANK] * 64, (NAME[prec], sizes)
+        assert infos == [0] * 64
+    del As
+    torch.cuda.empty_cache()
+
+
+def test_decision_rule_and_diagnostics(run, setup):
+    """keep j iff u_j < d_j on the GPU's own probabilities; loglik is the sum
+    of ln|d'_j|; the library's diagnostics (smallest |u_j - d_j|, count and
+    size of d_j outside [0, 1]) equal their recomputation from the outputs."""
     prec, res = run
     us = setup[4]
     for r, u in zip(res, us):
-        d = r["pivots"] + 1.0 - r["mask"]
+        d = np.where(r["mask"] == 1, r["pivots"], r["pivots"] + 1.0)
         assert np.array_equal(r["mask"], (u < d).astype(np.uint8))
         ll = float(np.sum(np.log(np.abs(r["pivots"]))))
         assert r["loglik"] == pytest.approx(ll, rel=1e-12)
+        gap = float(np.min(np.abs(u - d)))
+        outside = int(np.sum((d < -1e-12) | (d > 1.0 + 1e-12)))
+        far = float(np.max(np.maximum(-d, d - 1.0).clip(min=0.0)))
+        assert r["stats"][0] == gap
+        assert r["stats"][1] == outside
+        assert r["stats"][2] == far
+        # rounding pushes a probability out of [0, 1] by no more than the tolerance
+        assert far <= TOL[prec]
+    print(f"[accuracy] prec={NAME[prec]} d_j outside [-1e-12, 1+1e-12]: "
+          f"{sum(int(r['stats'][1]) for r in res)} over {BATCH} samples, worst by "
+          f"{max(r['stats'][2] for r in res):.3e}")
 
 
 def test_factor_reconstructs_sampled_entries(run, setup):
@@ -106,33 +183,19 @@ def test_factor_reconstructs_sampled_entries(run, setup):
             target = Kh[i, k] - (1.0 - r["mask"][i] if i == k else 0.0)
             scale = 1.0 + float(np.dot(np.abs(Li * d[:m]), np.abs(Lk)))
             worst = max(worst, abs(acc - target) / scale)
-            assert abs(acc - target) <= TOL[prec] * scale * 10, (i, k, acc, target)
-    print(f"[accuracy] prec={'split' if prec else 'fp64'} reconstruction max |LDL^T - (K - 1_Yc)| / scale = {worst:.3e}")
+            assert abs(acc - target) <= TOL[prec] * scale, (i, k, acc, target)
+    print(f"[accuracy] prec={NAME[prec]} reconstruction max |LDL^T - (K - 1_Yc)| / scale = {worst:.3e}")
 
 
-def test_prefix_matches_oracle(run, setup):
-    """The first p pivots of an oracle run with the same stream."""
-    prec, res = run
-    Kh, us = setup[3], setup[4]
-    p = 24
-    A = np.array(Kh.T, order="F", copy=True)
-    ref = oracle.ldlh(A, us[0], npiv=p, inplace=True)
-    r = res[0]
-    ref_pref = {"mask": ref["mask"][:p], "predec": ref["predec"][:p], "loglik": 0.0}
-    v = compare(r["mask"][:p], r["pivots"][:p], 0.0, ref_pref, us[0][:p], TOL[prec], THR[prec])
-    print(f"[accuracy] prec={'split' if prec else 'fp64'} first {p} pivots: max |d_gpu - d_oracle| = {v.max_dd:.3e}")
-    assert v.ok or v.near_tie, v.why
-    assert v.max_dd <= TOL[prec]
-
-
-@pytest.mark.parametrize("j", [700, 2500, 4000])
+@pytest.mark.parametrize("j", [700, 2500, 4000, 6000, 10000, 15000])
 def test_conditional_probability_deep_in_the_factorization(run, setup, j):
     """d_j from the GPU equals P[j in Y | the GPU's decisions for 0..j-1],
-    the Schur complement of Props. 3-5 evaluated with a library solve."""
+    the Schur complement of Props. 3-5 evaluated with a library solve; j
+    covers every 4096- (split) and 2048-column (FP64) outer panel."""
     prec, res = run
     Kh = setup[3]
     r = res[1]
     d_gpu = r["pivots"][j] + 1.0 - r["mask"][j]
     d_ref = oracle.conditional_pivot(Kh[: j + 1, : j + 1], r["mask"][:j], j)
-    print(f"[accuracy] prec={'split' if prec else 'fp64'} j={j} |d_gpu - d_ref| = {abs(d_gpu - d_ref):.3e}")
+    print(f"[accuracy] prec={NAME[prec]} j={j} |d_gpu - d_ref| = {abs(d_gpu - d_ref):.3e}")
     assert abs(d_gpu - d_ref) <= TOL[prec], (d_gpu, d_ref)

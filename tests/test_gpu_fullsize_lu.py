@@ -2,11 +2,12 @@
 K = S H S^-1 (diagonal similarity of a Hermitian H, Prop. 2), n = 8192, FP64
 storage, eight samples per batched call, both precisions.
 
-The checks are properties that hold at any size plus outputs the oracle (or the
-plain definition behind it) can compute one at a time:
+The checks:
+  - full-length parity: samples on streams 3000 and 3001 against whole oracle
+    runs on the same bytes and streams (every pivot and the log-likelihood,
+    under the near-tie rule of tests/parity.py);
   - info = 0; the decision rule on the GPU's own probabilities (keep iff
     u_j < d_j) and loglik = sum ln|d'_j|;
-  - the first pivots equal a bounded oracle run on the same bytes and stream;
   - at sampled j, d_j equals the conditional inclusion probability given the
     GPU's own decisions for 0..j-1, from K by a library solve (Props. 3-5);
   - sampled entries of L U equal K - 1_{Y^c};
@@ -46,9 +47,12 @@ def setup():
 def run(request, setup):
     B, dev, K, H, Kh, us = setup
     prec = request.param
-    As = [K.clone() for _ in range(BATCH)]
+    print(f"[fullsize-lu] {'split' if prec else 'fp64'}: {BATCH} samples, one batched call",
+          flush=True)
+    # out of place from the resident K, as the benchmark calls it
+    As = [torch.empty_like(K) for _ in range(BATCH)]
     uts = [torch.from_numpy(u).to(dev) for u in us]
-    outs = B.dpp_sample_lu_batched(As, uts, prec=prec)
+    outs = B.dpp_sample_lu_batched(As, uts, prec=prec, Ks=[K] * BATCH)
     Ah = H.clone()
     oh = B.dpp_sample_ldlh(Ah, uts[0], prec=prec)
     torch.cuda.synchronize()
@@ -74,20 +78,33 @@ def test_info_and_decision_rule(run, setup):
         assert r["loglik"] == pytest.approx(float(np.sum(np.log(np.abs(r["pivots"])))), rel=1e-12)
 
 
-def test_prefix_matches_oracle(run, setup):
+_ORACLE = {}
+
+
+def _oracle(Kh, us, i):
+    """A whole oracle run on stream 3000 + i, computed once per module."""
+    if i not in _ORACLE:
+        print(f"[fullsize-lu] oracle run on stream {3000 + i}", flush=True)
+        r = oracle.lu(np.array(Kh, order="F", copy=True), us[i], inplace=True)
+        _ORACLE[i] = {k: r[k] for k in ("mask", "predec", "loglik", "info")}
+    return _ORACLE[i]
+
+
+@pytest.mark.parametrize("i", [0, 1])
+def test_full_length_parity_with_oracle(run, setup, i):
     prec, res, _ = run
     Kh, us = setup[4], setup[5]
-    p = 24
-    ref = oracle.lu(np.array(Kh, order="F", copy=True), us[0], npiv=p, inplace=True)
-    r = res[0]
-    v = compare(r["mask"][:p], r["pivots"][:p], 0.0,
-                {"mask": ref["mask"][:p], "predec": ref["predec"][:p], "loglik": 0.0},
-                us[0][:p], TOL[prec], THR[prec])
-    print(f"[accuracy] LU prec={'split' if prec else 'fp64'} first {p} pivots: max |d_gpu - d_oracle| = {v.max_dd:.3e}")
-    assert (v.ok or v.near_tie) and v.max_dd <= TOL[prec]
+    ref = _oracle(Kh, us, i)
+    r = res[i]
+    assert ref["info"] == 0
+    v = compare(r["mask"], r["pivots"], r["loglik"], ref, us[i], TOL[prec], THR[prec])
+    print(f"[accuracy] LU prec={'split' if prec else 'fp64'} stream {3000 + i}, all {N} pivots: "
+          f"first mask diff {v.first_diff}, near tie {v.near_tie}, max |d_gpu - d_oracle| = "
+          f"{v.max_dd:.3e}, |dll|/|ll| = {v.ll_rel:.3e}, min |u - d| = {v.min_gap:.3e}")
+    assert v.ok, v.why
 
 
-@pytest.mark.parametrize("j", [500, 2000, 4000])
+@pytest.mark.parametrize("j", [500, 2000, 4000, 6000, 8000])
 def test_conditional_probability(run, setup, j):
     prec, res, _ = run
     Kh = setup[4]
@@ -114,7 +131,7 @@ def test_factor_reconstructs_sampled_entries(run, setup):
         acc += F[i, k] if i <= k else F[i, k] * F[k, k]
         target = Kh[i, k] - (1.0 - mask[i] if i == k else 0.0)
         scale = 1.0 + float(np.dot(np.abs(Li), np.abs(Uk)))
-        assert abs(acc - target) <= TOL[prec] * scale * 10, (i, k, acc, target)
+        assert abs(acc - target) <= TOL[prec] * scale, (i, k, acc, target)
 
 
 def test_same_dpp_as_hermitian_kernel(run, setup):
@@ -127,5 +144,5 @@ def test_same_dpp_as_hermitian_kernel(run, setup):
     v = compare(res[0]["mask"], res[0]["pivots"], res[0]["loglik"], ref, u0,
                 2 * TOL[prec], THR[prec])
     print(f"[accuracy] LU prec={'split' if prec else 'fp64'} mask(K) vs LDL^H mask(H): "
-          f"equal={v.ok} near_tie={v.near_tie} max |dd| = {v.max_dd:.3e}")
-    assert v.ok or v.near_tie, v.why
+          f"first diff {v.first_diff} near_tie={v.near_tie} max |dd| = {v.max_dd:.3e}")
+    assert v.ok, v.why

@@ -115,8 +115,13 @@ def test_lu_similarity_kernel_n1024(prec):
     u = W.uniform_stream(1024, seed=3000)
     v, got, ref = _check(False, K, u, prec)
     gh = _run(True, H, u, prec)
-    if v.first_diff < 0:
-        assert np.array_equal(got["mask"], gh["mask"]) or prec == 1
+    # Prop. 2 on the GPU alone: the LU run on K against the LDL^H run on H,
+    # each within the tolerance of the oracle, so within twice it of each other
+    t, h = TOL[prec]
+    w = compare(got["mask"], got["pivots"], got["loglik"],
+                {"mask": gh["mask"], "predec": gh["pivots"] + 1.0 - gh["mask"],
+                 "loglik": gh["loglik"]}, u, 2 * t, h)
+    assert w.ok, w.why
 
 
 def test_fp32_storage_lensemble():
@@ -412,7 +417,7 @@ def test_batched_lensembles_uneven_n_fp32(prec):
         ref = oracle.ldlh(np.asarray(K, dtype=np.float64), u)
         v = compare(o["mask"].cpu().numpy(), o["pivots"].cpu().numpy(), float(o["loglik"].cpu()[0]),
                     ref, u, tol, thr)
-        assert v.ok or v.near_tie, v.why
+        assert v.ok, v.why
         ties += int(v.near_tie)
         worst = max(worst, v.max_dd)
         assert int(o["mask"].sum().item()) <= 64
@@ -463,6 +468,109 @@ def test_greedy_ml_mode(prec):
     ref = oracle.ldlh(K, u)
     got = _run(True, K, u, prec)
     v = compare(got["mask"], got["pivots"], got["loglik"], ref, u, t, h)
-    assert v.ok or v.near_tie, v.why
+    assert v.ok, v.why
     d = got["pivots"] + 1.0 - got["mask"]
     assert np.array_equal(got["mask"], (d > 0.5).astype(np.uint8))
+
+
+_BIG = {}
+
+
+def _big_kernel(which):
+    """Kernels past the first outer panel (split: 4096 columns, FP64: 2048):
+    a projection kernel n = 6144 of rank 1536 and a dense Hermitian kernel
+    n = 8192, generated on the device; host copies for the oracle."""
+    if which not in _BIG:
+        if which == "proj6144":
+            K = W.projection_kernel(6144, 1536, seed=12, device=DEV)
+        else:
+            K = W.hermitian_kernel(8192, seed=21, device=DEV)
+        torch.cuda.synchronize()
+        _BIG[which] = (K, K.cpu().numpy(), {})
+    return _BIG[which]
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+@pytest.mark.parametrize("which", ["proj6144", "dense8192"])
+def test_ldlh_past_the_outer_panel(which, prec):
+    """Two samples of one resident K in a batched out-of-place call (the
+    benchmark's launch form), every pivot against whole oracle runs on the
+    same bytes and streams, at sizes whose later pivots depend on trailing
+    updates of the full outer-panel depth."""
+    K, Kh, cache = _big_kernel(which)
+    n = Kh.shape[0]
+    seeds = (21000, 21001)
+    us = [W.uniform_stream(n, seed=s) for s in seeds]
+    As = [torch.empty_like(K) for _ in seeds]
+    outs = B.dpp_sample_ldlh_batched([A.t() for A in As],
+                                     [torch.from_numpy(u).to(DEV) for u in us], prec=prec,
+                                     Ks=[K.t()] * len(seeds))
+    torch.cuda.synchronize()
+    t, h = TOL[prec]
+    for s, u, o in zip(seeds, us, outs):
+        if s not in cache:
+            r = oracle.ldlh(np.array(Kh.T, order="F", copy=True), u, inplace=True)
+            cache[s] = {k: r[k] for k in ("mask", "predec", "loglik", "info")}
+        ref = cache[s]
+        v = compare(o["mask"].cpu().numpy(), o["pivots"].cpu().numpy(),
+                    float(o["loglik"].cpu()[0]), ref, u, t, h)
+        print(f"[accuracy] {which} prec={PREC_ID[prec]} stream {s}: first mask diff "
+              f"{v.first_diff}, near tie {v.near_tie}, max |d - d_oracle| = {v.max_dd:.3e}, "
+              f"|dll|/|ll| = {v.ll_rel:.3e}")
+        assert int(o["info"].item()) == 0
+        assert v.ok, v.why
+        if which == "proj6144":
+            assert int(o["mask"].sum().item()) == 1536
+    del As, outs
+
+
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_nan_in_kernel_sets_info(herm, prec):
+    """A NaN in K reaches a pivot: info names the first NaN pivot (as the
+    oracle's does), loglik is NaN, and the pivots before it are unaffected.
+    A NaN on the diagonal at 70 is that pivot; one at (150, 3) (and (3, 150)
+    for LU) reaches pivot 150 through the updates of column 3."""
+    n = 200
+    for pos, first in (((70, 70), 70), ((150, 3), 150)):
+        K = W.hermitian_kernel(n, seed=160)
+        if not herm:
+            K = W.similarity_kernel(n, seed=160)[0]
+        K = np.array(K)
+        i, k = pos
+        K[i, k] = np.nan
+        K[k, i] = np.nan
+        u = W.uniform_stream(n, seed=16000)
+        ref = (oracle.ldlh if herm else oracle.lu)(K, u)
+        got = _run(herm, K, u, prec)
+        assert ref["info"] == first + 1
+        assert got["info"] == first + 1, (pos, got["info"])
+        assert np.isnan(got["loglik"])
+        t, h = TOL[prec]
+        pre = {"mask": ref["mask"][:first], "predec": ref["predec"][:first], "loglik": 0.0}
+        v = compare(got["mask"][:first], got["pivots"][:first], 0.0, pre, u[:first], t, h)
+        assert v.first_diff < 0 and v.max_dd <= t, v.why
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+def test_decision_diagnostics(prec):
+    """The library's per-problem diagnostics: the smallest |u_j - d_j| equals
+    the oracle's to the path's tolerance (the margin of the decisions), and
+    no probability leaves [0, 1] by more than the tolerance; partial problems
+    report over their decided indices only."""
+    n = 700
+    Ks = [W.hermitian_kernel(n, seed=170), W.hermitian_kernel(n, seed=171)]
+    us = [W.uniform_stream(n, seed=17000), W.uniform_stream(n, seed=17001)]
+    As = [B.colmajor(K, device=DEV) for K in Ks]
+    outs = B.dpp_sample_ldlh_batched(As, [torch.from_numpy(u).to(DEV) for u in us], prec=prec,
+                                     npivs=[0, 256])
+    torch.cuda.synchronize()
+    t, h = TOL[prec]
+    for K, u, o, npiv in zip(Ks, us, outs, (n, 256)):
+        st = o["stats"].cpu().numpy()
+        ref = oracle.ldlh(K, u, npiv=npiv)
+        gap = float(np.min(np.abs(u[:npiv] - ref["predec"][:npiv])))
+        assert abs(st[0] - gap) <= t, (st[0], gap)
+        d = ref["predec"][:npiv]
+        assert st[1] == pytest.approx(float(np.sum((d < -1e-12) | (d > 1 + 1e-12))), abs=2)
+        assert 0.0 <= st[2] <= t

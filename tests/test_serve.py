@@ -1,11 +1,14 @@
 """The serving loop: admission policy on the CPU; on the GPU, a served trace
-whose every result equals the standalone call (bit for bit) and whose batches
-overlapped on the device."""
+whose every result matches the oracle on the kernel's stored bytes and equals
+the standalone call (bit for bit), and whose batches overlapped on the
+device."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1905_00165_amd import serve
 from paper_1905_00165_amd import workloads as W
+from parity import compare
 
 torch = pytest.importorskip("torch")
 
@@ -55,6 +58,11 @@ def test_served_results_equal_standalone_and_overlap(prec):
     torch.cuda.synchronize()
     assert srv.batches > 3 and srv.max_inflight >= 2
     assert all(torch.equal(K, K0) for K, K0 in zip(kernels, before))  # resident kernels only read
+    # the oracle on each kernel's FP32 bytes widened to FP64 (FP32 storage:
+    # 1e-5 with FP64 updates, 1e-4 split; near-tie thresholds 1e-6 / 1e-5)
+    tol, thr = (1e-5, 1e-6) if prec == 0 else (1e-4, 1e-5)
+    host = [K.cpu().numpy().astype(np.float64) for K in kernels]
+    worst, ties = 0.0, 0
     for r in reqs:
         A = kernels[r.kernel].clone()
         alone = B.dpp_sample_ldlh(A, r.u, prec=prec)
@@ -64,6 +72,14 @@ def test_served_results_equal_standalone_and_overlap(prec):
         assert torch.equal(alone["pivots"], r.pivots), r.rid
         assert torch.equal(alone["loglik"], r.loglik), r.rid
         assert int(r.mask.sum().item()) <= 64
+        u = r.u.cpu().numpy()
+        ref = oracle.ldlh(host[r.kernel], u)
+        v = compare(r.mask.cpu().numpy(), r.pivots.cpu().numpy(), float(r.loglik.cpu()[0]),
+                    ref, u, tol, thr)
+        assert v.ok, (r.rid, v.why)
+        worst = max(worst, v.max_dd)
+        ties += int(v.near_tie)
+    print(f"[accuracy] served prec={prec}: max |d - d_oracle| = {worst:.3e}, near ties {ties}")
     st = serve.latency_stats(reqs)
     print(f"[serve] prec={prec} batches={srv.batches} max_inflight={srv.max_inflight} "
           f"p50={st['p50_ms']:.2f} ms p99={st['p99_ms']:.2f} ms")
