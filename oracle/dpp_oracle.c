@@ -158,3 +158,102 @@ int dpp_oracle_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Complex kernels (Sec. 1 examples built on complex kernels; Sec. 3, the
+ * dense complex LU experiment). Same listing, complex arithmetic. Storage is
+ * interleaved (real, imaginary) doubles, column-major, leading dimension lda
+ * counted in complex entries.
+ *
+ * Readings of points the paper leaves open for complex kernels:
+ *   - a conditional inclusion probability is real, so the imaginary part of
+ *     a computed diagonal entry is rounding residue: the Bernoulli decision,
+ *     the returned pivots and predec and the likelihood use the real part;
+ *     d'_j = Re(A[j,j]) on keeping, Re(A[j,j]) - 1 on rejecting;
+ *   - LU scales the column by the whole complex pivot (A[j,j], or A[j,j] - 1),
+ *     so L U is exactly the computed factorization of K - 1_{Y^c};
+ *   - LDL^H (Hermitian K, lower triangle): D is real, the diagonal entries'
+ *     imaginary parts are never read, and the stored diagonal is d'_j + 0i;
+ *     the update subtracts l_i d'_j conj(l_k), i.e. the scaled column times
+ *     the conjugate of the unscaled one;
+ *   - info: the first j with Re(d'_j) == 0 or a NaN part.
+ */
+#include <complex.h>
+
+#define ZAT(A, lda, i, k) ((A)[(size_t)(i) + (size_t)(k) * (size_t)(lda)])
+
+static int zbad(double complex p) { return creal(p) == 0.0 || isnan(creal(p)) || isnan(cimag(p)); }
+
+int dpp_oracle_zlu(double* Araw, int64_t n, int64_t lda, const double* u, int64_t npiv,
+                   uint8_t* mask, double* pivots, double* predec, double* loglik, int32_t* info)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || !Araw || !u || !mask || !pivots || !loglik || !info)
+        return 1;
+    double complex* A = (double complex*)Araw;
+    if (npiv <= 0 || npiv > n) npiv = n;
+    double ll = 0.0;
+    int32_t inf = 0;
+    for (int64_t j = 0; j < npiv; ++j) {
+        const double complex a = ZAT(A, lda, j, j);
+        const double d = creal(a);
+        if (predec) predec[j] = d;
+        uint8_t keep;
+        const double dp = decide(d, u[j], &keep);
+        mask[j] = keep;
+        const double complex p = keep ? a : a - 1.0;
+        ZAT(A, lda, j, j) = p;
+        pivots[j] = dp;
+        ll += log(fabs(dp));
+        if (inf == 0 && zbad(p)) inf = (int32_t)(j + 1);
+        for (int64_t i = j + 1; i < n; ++i) ZAT(A, lda, i, j) /= p;
+#pragma omp parallel for schedule(static)
+        for (int64_t k = j + 1; k < n; ++k) {
+            const double complex ujk = ZAT(A, lda, j, k);
+            double complex* colk = &ZAT(A, lda, 0, k);
+            const double complex* colj = &ZAT(A, lda, 0, j);
+            for (int64_t i = j + 1; i < n; ++i) colk[i] -= colj[i] * ujk;
+        }
+    }
+    *loglik = ll;
+    *info = inf;
+    return 0;
+}
+
+/* Hermitian complex kernel, lower triangle; row_j: 2n doubles of scratch. */
+int dpp_oracle_zldlh(double* Araw, int64_t n, int64_t lda, const double* u, int64_t npiv,
+                     uint8_t* mask, double* pivots, double* predec, double* loglik,
+                     int32_t* info, double* row_raw)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || !Araw || !u || !mask || !pivots || !loglik || !info ||
+        !row_raw)
+        return 1;
+    double complex* A = (double complex*)Araw;
+    double complex* row_j = (double complex*)row_raw;
+    if (npiv <= 0 || npiv > n) npiv = n;
+    double ll = 0.0;
+    int32_t inf = 0;
+    for (int64_t j = 0; j < npiv; ++j) {
+        const double d = creal(ZAT(A, lda, j, j));
+        if (predec) predec[j] = d;
+        const double dp = decide(d, u[j], &mask[j]);
+        ZAT(A, lda, j, j) = dp;
+        pivots[j] = dp;
+        ll += log(fabs(dp));
+        if (inf == 0 && (dp == 0.0 || isnan(dp))) inf = (int32_t)(j + 1);
+        /* row_j[k] = A[j,k] = conj(A[k,j]) (unscaled), then A[j+1:n, j] /= d'_j */
+        for (int64_t k = j + 1; k < n; ++k) {
+            row_j[k] = conj(ZAT(A, lda, k, j));
+            ZAT(A, lda, k, j) /= dp;
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t k = j + 1; k < n; ++k) {
+            const double complex ajk = row_j[k];
+            double complex* colk = &ZAT(A, lda, 0, k);
+            const double complex* colj = &ZAT(A, lda, 0, j);
+            for (int64_t i = k; i < n; ++i) colk[i] -= colj[i] * ajk;
+        }
+    }
+    *loglik = ll;
+    *info = inf;
+    return 0;
+}

@@ -33,6 +33,10 @@ def load_library():
     lib.dpp_oracle_lu.restype = ctypes.c_int
     lib.dpp_oracle_ldlh.argtypes = common + [_dp]
     lib.dpp_oracle_ldlh.restype = ctypes.c_int
+    lib.dpp_oracle_zlu.argtypes = common
+    lib.dpp_oracle_zlu.restype = ctypes.c_int
+    lib.dpp_oracle_zldlh.argtypes = common + [_dp]
+    lib.dpp_oracle_zldlh.restype = ctypes.c_int
     lib.dpp_oracle_threads.argtypes = []
     lib.dpp_oracle_threads.restype = ctypes.c_int
     _lib = lib
@@ -48,11 +52,13 @@ def _run(fn_name, K, u, npiv, inplace):
     K = np.asarray(K)
     n = K.shape[0]
     assert K.shape == (n, n)
+    cplx = fn_name.startswith("dpp_oracle_z")
+    dt = np.complex128 if cplx else np.float64
     if inplace:
-        assert K.dtype == np.float64 and K.flags.f_contiguous
+        assert K.dtype == dt and K.flags.f_contiguous
         A = K
     else:
-        A = np.array(K, dtype=np.float64, order="F", copy=True)
+        A = np.array(K, dtype=dt, order="F", copy=True)
     u = np.ascontiguousarray(u, dtype=np.float64)
     assert u.shape[0] >= n
     mask = np.zeros(n, dtype=np.uint8)
@@ -63,8 +69,8 @@ def _run(fn_name, K, u, npiv, inplace):
     args = [A.ctypes.data_as(_dp), n, max(n, 1), u.ctypes.data_as(_dp),
             int(npiv or 0), mask.ctypes.data_as(_u8p), piv.ctypes.data_as(_dp),
             pre.ctypes.data_as(_dp), ctypes.byref(ll), ctypes.byref(info)]
-    if fn_name == "dpp_oracle_ldlh":
-        row = np.zeros(max(n, 1), dtype=np.float64)
+    if fn_name in ("dpp_oracle_ldlh", "dpp_oracle_zldlh"):
+        row = np.zeros(max(n, 1), dtype=dt)
         args.append(row.ctypes.data_as(_dp))
     rc = getattr(lib, fn_name)(*args)
     if rc != 0:
@@ -84,6 +90,19 @@ def lu(K, u, npiv=None, inplace=False):
     return _run("dpp_oracle_lu", K, u, npiv, inplace)
 
 
+def zldlh(K, u, npiv=None, inplace=False):
+    """Complex Hermitian sampler (lower triangle of a complex128 K). Decisions,
+    pivots, predec and loglik use the real parts of the diagonal entries (a
+    conditional probability is real); A holds the complex L and the real D."""
+    return _run("dpp_oracle_zldlh", K, u, npiv, inplace)
+
+
+def zlu(K, u, npiv=None, inplace=False):
+    """Complex non-Hermitian sampler (all of a complex128 K); outputs as zldlh,
+    A holds the complex L and U (U's diagonal: the complex pivots)."""
+    return _run("dpp_oracle_zlu", K, u, npiv, inplace)
+
+
 def conditional_pivot(K, mask_prefix, j):
     """d_j given the decisions on indices 0..j-1, straight from Props. 3-5:
     the marginal kernel of the DPP on the remaining indices conditioned on the
@@ -91,12 +110,15 @@ def conditional_pivot(K, mask_prefix, j):
     A = [0, j), so
         d_j = K_jj - K_{j,A} (K_A - diag(1 - mask_A))^{-1} K_{A,j}.
     Uses a library solve; cost O(j^3)."""
-    K = np.asarray(K, dtype=np.float64)
+    K = np.asarray(K)
+    if not np.iscomplexobj(K):
+        K = np.asarray(K, dtype=np.float64)
     if j == 0:
-        return float(K[0, 0])
+        return float(np.real(K[0, 0]))
     KA = K[:j, :j] - np.diag(1.0 - np.asarray(mask_prefix[:j], dtype=np.float64))
     x = np.linalg.solve(KA, K[:j, j])
-    return float(K[j, j] - K[j, :j] @ x)
+    # a conditional probability is real; for complex K the imaginary part is rounding
+    return float(np.real(K[j, j] - K[j, :j] @ x))
 
 
 def conditional_kernel(K, mask_prefix):
@@ -121,14 +143,20 @@ def lensemble_marginal(L):
 
 
 def reconstruct_ldlh(A):
-    """L D L^T from a factored lower triangle (strict lower = L, diagonal = D)."""
-    A = np.asarray(A, dtype=np.float64)
+    """L D L^H from a factored lower triangle (strict lower = L, diagonal = D;
+    real or complex, D real)."""
+    A = np.asarray(A)
+    if not np.iscomplexobj(A):
+        A = np.asarray(A, dtype=np.float64)
     L = np.tril(A, -1) + np.eye(A.shape[0])
-    return (L * np.diag(A)) @ L.T
+    return (L * np.real(np.diag(A))) @ L.conj().T
 
 
 def reconstruct_lu(A):
-    """L U from an in-place unpivoted LU (strict lower = L, upper = U)."""
-    A = np.asarray(A, dtype=np.float64)
+    """L U from an in-place unpivoted LU (strict lower = L, upper = U; real or
+    complex)."""
+    A = np.asarray(A)
+    if not np.iscomplexobj(A):
+        A = np.asarray(A, dtype=np.float64)
     L = np.tril(A, -1) + np.eye(A.shape[0])
     return L @ np.triu(A)

@@ -41,12 +41,25 @@ def _orthonormal(rng, rows: int, cols: int) -> np.ndarray:
     return Q
 
 
-def hermitian_kernel(n: int, seed: int) -> np.ndarray:
-    """K = Q diag(lam) Q^T with Q from QR of N(0,1) n x n and lam_i ~ U(0,1)."""
+def hermitian_kernel(n: int, seed: int, device=None):
+    """K = Q diag(lam) Q^T with Q from QR of N(0,1) n x n and lam_i ~ U(0,1).
+
+    With ``device`` (a torch CUDA device) the QR and the product run there in
+    FP64 from the same host draws, and a column-major device tensor is
+    returned (the same construction; the bytes differ from the host path's)."""
     rng = np.random.default_rng(seed)
-    Q = _orthonormal(rng, n, n)
+    if device is None:
+        Q = _orthonormal(rng, n, n)
+        lam = rng.random(n)
+        return np.asfortranarray(symmetrize_lower((Q * lam) @ Q.T))
+    import torch
+    G = rng.standard_normal((n, n))
     lam = rng.random(n)
-    return np.asfortranarray(symmetrize_lower((Q * lam) @ Q.T))
+    Q, _ = torch.linalg.qr(torch.from_numpy(G).to(device), mode="reduced")
+    K = (Q * torch.from_numpy(lam).to(device)) @ Q.T
+    del Q
+    K = torch.tril(K) + torch.tril(K, -1).T
+    return K.T.contiguous().T
 
 
 def projection_kernel(n: int, rank: int, seed: int, device=None):
@@ -174,3 +187,79 @@ def grid_transfer_current_kernel(d: int):
     Br = B[1:, :]
     K = Br.T @ np.linalg.solve(Br @ Br.T, Br)
     return np.asfortranarray(symmetrize_lower(K)), edges
+
+
+# ------------------------------------------------------------ complex kernels
+
+def _complex_orthonormal(rng, n: int):
+    """Q factor of the QR of a seeded complex Gaussian n x n matrix (real and
+    imaginary parts N(0, 1/2))."""
+    G = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    Q, _ = np.linalg.qr(G)
+    return Q
+
+
+def hermitize_lower(K: np.ndarray) -> np.ndarray:
+    """Copy the conjugate of the strict lower triangle onto the upper one and
+    drop the diagonal's imaginary parts, so K is exactly Hermitian."""
+    return np.tril(K, -1) + np.tril(K, -1).conj().T + np.diag(np.real(np.diag(K)))
+
+
+def complex_hermitian_kernel(n: int, seed: int, beta: bool = False) -> np.ndarray:
+    """K = Q diag(lam) Q^H, Q unitary from QR of a complex Gaussian matrix,
+    lam_i ~ U(0, 1) (or Beta(0.5, 2) with `beta`); complex128, column-major."""
+    rng = np.random.default_rng(seed)
+    Q = _complex_orthonormal(rng, n)
+    lam = rng.beta(0.5, 2.0, size=n) if beta else rng.random(n)
+    return np.asfortranarray(hermitize_lower((Q * lam) @ Q.conj().T))
+
+
+def complex_similarity_kernel(n: int, seed: int, unit_modulus: bool = False):
+    """A non-Hermitian complex kernel of the same DPP as a complex Hermitian
+    one (Prop. 2): H as in complex_hermitian_kernel with lam ~ Beta(0.5, 2),
+    S = diag(exp(z_j + i theta_j)), z ~ N(0, 0.5) (standard deviation 0.5),
+    theta ~ U(0, 2 pi), K = S H S^{-1}. With `unit_modulus`, z = 0 and K is
+    Hermitian again. Returns (K, H), complex128, column-major."""
+    H = complex_hermitian_kernel(n, seed, beta=True)
+    rng = np.random.default_rng(seed + 7_000_000)
+    z = np.zeros(n) if unit_modulus else rng.normal(0.0, 0.5, size=n)
+    theta = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    s = np.exp(z + 1j * theta)
+    K = (s[:, None] * H) / s[None, :]
+    if unit_modulus:
+        K = hermitize_lower(K)
+    return np.asfortranarray(K), H
+
+
+def aztec_diamond_kernel(d: int):
+    """Kenyon's dimer kernel of the Aztec diamond of order d (the paper's
+    domino-tiling examples, Sec. 1): a complex, non-Hermitian marginal kernel
+    whose DPP is the uniform measure on domino tilings.
+
+    Squares: the unit squares [x, x+1] x [y, y+1] with |x + 1/2| + |y + 1/2| <= d,
+    black when x + y is even. Ground set: the (black, white) adjacent pairs
+    (a domino covering both). Kasteleyn matrix C[b, w] = 1 for a horizontal
+    pair, i for a vertical one (every 4-cycle around an interior lattice point
+    then has alternating product -1, Kasteleyn's condition), and the kernel is
+    L[e, f] = C[b_e, w_e] (C^{-1})[w_e, b_f] (Kenyon's local statistics). Every
+    sample is a perfect matching of the squares (d(d+1) dominoes), and each of
+    the 2^{d(d+1)/2} tilings has likelihood 2^{-d(d+1)/2}.
+    Returns (K complex128 column-major, black index per edge, white index per
+    edge, C)."""
+    sq = [(x, y) for x in range(-d, d) for y in range(-d, d) if abs(x + 0.5) + abs(y + 0.5) <= d]
+    black = {s: i for i, s in enumerate(s for s in sq if (s[0] + s[1]) % 2 == 0)}
+    white = {s: i for i, s in enumerate(s for s in sq if (s[0] + s[1]) % 2 != 0)}
+    eb, ew, wt = [], [], []
+    for (x, y), b in black.items():
+        for dx, dy, w in ((1, 0, 1.0), (-1, 0, 1.0), (0, 1, 1j), (0, -1, 1j)):
+            t = (x + dx, y + dy)
+            if t in white:
+                eb.append(b)
+                ew.append(white[t])
+                wt.append(w)
+    eb, ew, wt = np.array(eb), np.array(ew), np.array(wt, dtype=np.complex128)
+    C = np.zeros((len(black), len(white)), dtype=np.complex128)
+    C[eb, ew] = wt
+    Ci = np.linalg.inv(C)
+    K = wt[:, None] * Ci[ew][:, eb]
+    return np.asfortranarray(K), eb, ew, C

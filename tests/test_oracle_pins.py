@@ -383,3 +383,153 @@ def test_uniform_spanning_tree_of_the_40x40_grid():
     B[edges[:, 1], np.arange(len(edges))] = -1
     _, logtau = np.linalg.slogdet((B @ B.T)[1:, 1:])
     assert res["loglik"] == pytest.approx(-logtau, rel=1e-9)
+
+
+# ------------------------------------------------------------- complex kernels
+
+ZSAMPLERS = {"zldlh": oracle.zldlh, "zlu": oracle.zlu}
+
+
+def _zkernel(which, n, seed):
+    if which == "zldlh":
+        return W.complex_hermitian_kernel(n, seed)
+    return W.complex_similarity_kernel(n, seed)[0]
+
+
+@pytest.mark.parametrize("which", ["zldlh", "zlu"])
+def test_complex_forced_streams_enumerate_the_dpp_law(which):
+    """Complex kernels (a Hermitian Q diag(lam) Q^H, and a non-Hermitian
+    diagonal similarity of one with complex entries): for every S of [8] the
+    forced stream returns S with likelihood |det(K - 1_{S^c})| (library
+    complex determinant), and the 2^8 likelihoods sum to 1."""
+    n = 8
+    K = _zkernel(which, n, 111)
+    total = 0.0
+    for S in _all_masks(n):
+        res = ZSAMPLERS[which](K, _forced_stream(S))
+        assert np.array_equal(res["mask"], S)
+        p = _p_exact(K, S)
+        assert np.exp(res["loglik"]) == pytest.approx(p, rel=1e-10)
+        total += np.exp(res["loglik"])
+    assert total == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("which", ["zldlh", "zlu"])
+def test_complex_monte_carlo_law(which):
+    """Seeded streams: chi-square of the 2^5 subset frequencies against
+    |det(K - 1_{S^c})| and z-scores of the one- and two-point inclusion
+    frequencies against Re K_ii and K_ii K_jj - K_ij K_ji (real for a DPP)."""
+    n, N = 5, 40000
+    K = _zkernel(which, n, 211)
+    U = np.random.default_rng(213).random((N, n))
+    fn = ZSAMPLERS[which]
+    M = np.array([fn(K, U[t])["mask"] for t in range(N)], dtype=np.int64)
+    counts = np.bincount(M @ (1 << np.arange(n)), minlength=1 << n)
+    masks = np.array([[(c >> i) & 1 for i in range(n)] for c in range(1 << n)], dtype=np.uint8)
+    P = np.array([_p_exact(K, S) for S in masks])
+    chi2 = np.sum((counts - N * P) ** 2 / (N * P))
+    assert stats.chi2.sf(chi2, df=(1 << n) - 1) > 1e-4
+    kd = np.real(np.diag(K))
+    z = (M.mean(axis=0) - kd) / np.sqrt(kd * (1 - kd) / N)
+    assert np.all(np.abs(z) < 5)
+    for i, j in [(0, 1), (1, 4), (2, 3)]:
+        pij = np.real(K[i, i] * K[j, j] - K[i, j] * K[j, i])
+        assert abs(np.imag(K[i, i] * K[j, j] - K[i, j] * K[j, i])) < 1e-12
+        fij = np.mean(M[:, i] * M[:, j])
+        assert abs(fij - pij) / np.sqrt(pij * (1 - pij) / N) < 5
+
+
+@pytest.mark.parametrize("which", ["zldlh", "zlu"])
+def test_complex_path_on_a_real_kernel_is_the_real_oracle(which):
+    """A real symmetric (or real non-symmetric) kernel stored as complex: the
+    complex sampler reduces to the real one, bit for bit (every imaginary
+    part stays zero), so it inherits the real oracle's pins."""
+    n = 90
+    if which == "zldlh":
+        K = W.hermitian_kernel(n, seed=221)
+        real = oracle.ldlh(K, W.uniform_stream(n, seed=222))
+    else:
+        K = W.similarity_kernel(n, seed=221)[0]
+        real = oracle.lu(K, W.uniform_stream(n, seed=222))
+    res = ZSAMPLERS[which](K.astype(np.complex128), W.uniform_stream(n, seed=222))
+    assert np.array_equal(res["mask"], real["mask"])
+    np.testing.assert_array_equal(res["pivots"], real["pivots"])
+    assert res["loglik"] == real["loglik"]
+    part = np.tril if which == "zldlh" else (lambda x: x)
+    np.testing.assert_array_equal(np.real(part(res["A"])), part(real["A"]))
+    assert np.all(np.imag(part(res["A"])) == 0)
+
+
+def test_complex_unit_modulus_similarity_keeps_the_samples():
+    """Prop. 2 for complex kernels: K = D H D^{-1} with unit-modulus diagonal D
+    is Hermitian again and defines the same DPP; with a shared stream the
+    LDL^H sampler returns the same mask and likelihood on K and H, and so does
+    the LU sampler on a general complex similarity S H S^{-1}."""
+    n = 100
+    K, H = W.complex_similarity_kernel(n, seed=231, unit_modulus=True)
+    G, H2 = W.complex_similarity_kernel(n, seed=231)
+    np.testing.assert_array_equal(H, H2)
+    assert np.allclose(K, K.conj().T, atol=0)
+    for s in range(4):
+        u = W.uniform_stream(n, seed=2310 + s)
+        a, b, c = oracle.zldlh(K, u), oracle.zldlh(H, u), oracle.zlu(G, u)
+        assert np.array_equal(a["mask"], b["mask"]) and np.array_equal(b["mask"], c["mask"])
+        assert a["loglik"] == pytest.approx(b["loglik"], rel=1e-10)
+        assert c["loglik"] == pytest.approx(b["loglik"], rel=1e-10)
+        np.testing.assert_allclose(c["predec"], b["predec"], atol=1e-10)
+
+
+@pytest.mark.parametrize("which", ["zldlh", "zlu"])
+def test_complex_factor_reconstructs_k_minus_indicator(which):
+    """A holds the factorization of K - 1_{Y^c}: L D L^H (D real) or L U."""
+    n = 70
+    K = _zkernel(which, n, 241)
+    u = W.uniform_stream(n, seed=242)
+    res = ZSAMPLERS[which](K, u)
+    target = K - np.diag(1.0 - res["mask"])
+    if which == "zldlh":
+        R = oracle.reconstruct_ldlh(res["A"])
+        np.testing.assert_allclose(np.tril(R), np.tril(target), atol=1e-12)
+        np.testing.assert_array_equal(np.imag(np.diag(res["A"])), 0.0)
+    else:
+        np.testing.assert_allclose(oracle.reconstruct_lu(res["A"]), target, atol=1e-12)
+    sign, logdet = np.linalg.slogdet(target)
+    assert res["loglik"] == pytest.approx(logdet, rel=1e-10)
+    np.testing.assert_array_equal(res["pivots"], np.real(np.diag(res["A"])))
+
+
+def test_complex_conditional_pivot_matches_enumeration():
+    """oracle.conditional_pivot on a complex kernel equals the conditional
+    inclusion probability from brute-force enumeration."""
+    n = 6
+    K = W.complex_similarity_kernel(n, seed=251)[0]
+    masks = np.array(list(_all_masks(n)))
+    P = np.array([_p_exact(K, S) for S in masks])
+    rng = np.random.default_rng(252)
+    for j in range(1, n):
+        hist = rng.integers(0, 2, size=j).astype(np.uint8)
+        consistent = np.all(masks[:, :j] == hist, axis=1)
+        p_cond = P[consistent & (masks[:, j] == 1)].sum() / P[consistent].sum()
+        assert oracle.conditional_pivot(K, hist, j) == pytest.approx(p_cond, rel=1e-9)
+
+
+def test_aztec_diamond_order_10():
+    """The paper's order-10 Aztec diamond example (Kenyon's kernel over the
+    Kasteleyn matrix, complex and non-Hermitian): every sample is a domino
+    tiling (each square covered once) with likelihood exp(-38.1231) as
+    printed, i.e. 2^{-55}: the uniform law over the 2^{d(d+1)/2} tilings."""
+    gold = json.load(open(GOLDEN))["aztec_diamond_10"]
+    d = gold["order"]
+    K, eb, ew, C = W.aztec_diamond_kernel(d)
+    assert K.shape == (4 * d * d, 4 * d * d)
+    # the Kasteleyn weighting counts the tilings: |det C| = 2^{d(d+1)/2}
+    assert np.linalg.slogdet(C)[1] == pytest.approx(d * (d + 1) / 2 * np.log(2), rel=1e-12)
+    for s in range(3):
+        res = oracle.zlu(K, W.uniform_stream(K.shape[0], seed=9100 + s))
+        assert res["info"] == 0
+        m = res["mask"].astype(bool)
+        assert m.sum() == d * (d + 1)
+        assert np.array_equal(np.sort(eb[m]), np.arange(d * (d + 1)))
+        assert np.array_equal(np.sort(ew[m]), np.arange(d * (d + 1)))
+        assert res["loglik"] == pytest.approx(gold["loglik_printed"], abs=5e-5)
+        assert res["loglik"] == pytest.approx(-d * (d + 1) / 2 * np.log(2), rel=1e-9)
