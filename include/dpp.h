@@ -61,10 +61,20 @@ typedef enum { DPP_F64 = 0, DPP_F32 = 1 } dpp_dtype;
    DPP_PREC_FP64: FP64 MFMA products, FP64 accumulation.
    DPP_PREC_SPLIT_BF16: each factor x is split as x = hi + lo with hi = bf16(x)
    and lo = bf16(x - hi); the update is hi*hi' + hi*lo' + lo*hi' on BF16 MFMA
-   with FP32 accumulation, subtracted from the stored value in the storage
+   with FP32 accumulation (about 2^-16 of each product is lost).
+   DPP_PREC_SPLIT_BF16X6: three pieces p0 = bf16(x), p1 = bf16(x - p0),
+   p2 = bf16(x - p0 - p1) and the six products p0*p0' + p0*p1' + p1*p0' +
+   p0*p2' + p2*p0' + p1*p1' on BF16 MFMA with FP32 accumulation (about 2^-24
+   of each product is lost, the FP32 accumulation's own order), at twice the
+   matrix-core work of DPP_PREC_SPLIT_BF16.
+   Every form subtracts the sum from the stored value in the storage
    precision. The diagonal-block decisions, the panel solves and the
-   log-likelihood stay in FP64 on both paths. */
-typedef enum { DPP_PREC_FP64 = 0, DPP_PREC_SPLIT_BF16 = 1 } dpp_precision;
+   log-likelihood stay in FP64 on every path. */
+typedef enum {
+    DPP_PREC_FP64 = 0,
+    DPP_PREC_SPLIT_BF16 = 1,
+    DPP_PREC_SPLIT_BF16X6 = 2
+} dpp_precision;
 
 /*
  * dpp_sample_ldlh - sample DPP(K) for Hermitian (real symmetric) K.

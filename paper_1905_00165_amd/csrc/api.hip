@@ -40,7 +40,7 @@ using dpp::kLeaf;
 struct Plan {
     bool herm;
     int dtype;   // 0 FP64 storage, 1 FP32 storage
-    bool split;  // split-BF16 updates
+    int pieces;  // split-BF16 updates: BF16 pieces per value (2 or 3), 0: FP64 updates
     int B0;      // outer panel width (kLeaf times a power of two)
     int ss;      // row stride of the split panel copies (elements)
 };
@@ -50,14 +50,14 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     Plan p;
     p.herm = herm;
     p.dtype = (dt == DPP_F32) ? 1 : 0;
-    p.split = (prec == DPP_PREC_SPLIT_BF16);
+    p.pieces = prec == DPP_PREC_SPLIT_BF16 ? 2 : prec == DPP_PREC_SPLIT_BF16X6 ? 3 : 0;
     // Outer panel width: each trailing update reads and writes the trailing
     // matrix once, so its HBM traffic per sample is ~ 8 n^3 / (3 B0) bytes for
     // FP64 storage; the split path needs the wider panel to stay MFMA-bound.
     // LU's rank-64 steps inside a panel touch ~ (n - j0) B0 / 2 entries of the
     // panel and ~ (n - j1) B0 / 2 of the rows of U to its right, against
     // (n - j1)^2 per trailing update; B0 = 512 balances them at n = 8192.
-    if (herm) p.B0 = p.split ? 4096 : 2048;
+    if (herm) p.B0 = p.pieces ? 4096 : 2048;
     else p.B0 = 512;
     // The split copies hold the columns of one outer panel, at most B0 and no
     // more than the largest problem has (rounded to whole blocks), so small
@@ -77,8 +77,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 size_t split_bytes(const Plan& p, int64_t n)
 {
-    return p.split ? align_up((size_t)4 * (size_t)dpp::plane_rows(n) * (size_t)p.ss * sizeof(uint16_t))
-                   : 0;
+    return p.pieces ? align_up((size_t)(2 * p.pieces) * (size_t)dpp::plane_rows(n) * (size_t)p.ss *
+                               sizeof(uint16_t))
+                    : 0;
 }
 size_t diag_bytes(int64_t n)
 {
@@ -92,7 +93,7 @@ size_t desc_bytes(int64_t count) { return align_up((size_t)count * sizeof(DevPro
 bool valid_enums(dpp_dtype dt, dpp_precision prec)
 {
     return (dt == DPP_F64 || dt == DPP_F32) &&
-           (prec == DPP_PREC_FP64 || prec == DPP_PREC_SPLIT_BF16);
+           (prec == DPP_PREC_FP64 || prec == DPP_PREC_SPLIT_BF16 || prec == DPP_PREC_SPLIT_BF16X6);
 }
 
 // gfx950 check, cached per device ordinal.
@@ -115,11 +116,12 @@ dpp_status device_ok()
 // ------------------------------------------------------------------ profiling
 // Kernel families whose launches the profiler tells apart.
 enum KernelId {
-    K_LEAF_LDLH, K_LEAF_LU, K_UPDATE_F64, K_UPDATE_BF16X3, K_STORE_DIAG, K_FINALIZE, K_DESCS,
-    K_COUNT
+    K_LEAF_LDLH, K_LEAF_LU, K_UPDATE_F64, K_UPDATE_BF16X3, K_UPDATE_BF16X6, K_STORE_DIAG,
+    K_FINALIZE, K_DESCS, K_COUNT
 };
-const char* const kKernelNames[K_COUNT] = {"leaf_ldlh", "leaf_lu",    "update_f64", "update_bf16x3",
-                                           "store_diag", "finalize", "store_descs"};
+const char* const kKernelNames[K_COUNT] = {"leaf_ldlh",     "leaf_lu",    "update_f64",
+                                           "update_bf16x3", "update_bf16x6", "store_diag",
+                                           "finalize",      "store_descs"};
 
 struct ProfRecord {
     int id;
@@ -192,7 +194,7 @@ void update_work(const Ctx& c, const dpp::Region& rg, int kw, double& flops, dou
 {
     flops = bytes = 0.0;
     const double elt = c.plan.dtype == 0 ? 8.0 : 4.0;
-    const double opnd = c.plan.split ? 4.0 : elt;  // hi+lo bf16, or one stored value
+    const double opnd = c.plan.pieces ? 2.0 * c.plan.pieces : elt;  // bf16 pieces, or one stored value
     for (int64_t n : *c.ns) {
         const int64_t nr = (rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n) - rg.r0;
         const int64_t nc = (rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n) - rg.c0;
@@ -214,7 +216,7 @@ void leaf_work(const Ctx& c, int64_t c0, double& flops, double& bytes)
         const double bs = (double)((n - c0) < kLeaf ? (n - c0) : kLeaf);
         const double m = (double)(n - c0) - bs;
         flops += bs * bs * bs / 3.0 * (c.plan.herm ? 1.0 : 2.0) + sides * m * bs * bs;
-        bytes += (bs * bs + 2.0 * sides * m * bs) * elt + (c.plan.split ? sides * m * bs * 8.0 : 0.0);
+        bytes += (bs * bs + 2.0 * sides * m * bs) * elt + sides * m * bs * 4.0 * c.plan.pieces;
     }
 }
 
@@ -222,10 +224,10 @@ dpp_status update(const Ctx& c, const dpp::Region& rg, int64_t k0, int kw, int64
 {
     double fl = 0, by = 0;
     if (c.profiling) update_work(c, rg, kw, fl, by);
-    if (c.plan.split)
-        return timed(c, K_UPDATE_BF16X3, fl, by, [&] {
-            return dpp::launch_update_bf16x3(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax,
-                                             rg, k0, kw, j0, c.plan.ss, c.s);
+    if (c.plan.pieces)
+        return timed(c, c.plan.pieces == 2 ? K_UPDATE_BF16X3 : K_UPDATE_BF16X6, fl, by, [&] {
+            return dpp::launch_update_split(c.plan.herm, c.plan.dtype, c.plan.pieces, c.probs,
+                                            c.count, c.nmax, rg, k0, kw, j0, c.plan.ss, c.s);
         });
     return timed(c, K_UPDATE_F64, fl, by, [&] {
         return dpp::launch_update_f64(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax, rg,
@@ -239,11 +241,11 @@ dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
     if (c.profiling) leaf_work(c, c0, fl, by);
     if (c.plan.herm)
         return timed(c, K_LEAF_LDLH, fl, by, [&] {
-            return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.split, c.probs, c.count, c.nmax, c0,
+            return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.pieces, c.probs, c.count, c.nmax, c0,
                                          j0, c.plan.ss, c.s);
         });
     return timed(c, K_LEAF_LU, fl, by, [&] {
-        return dpp::launch_leaf_lu(c.plan.dtype, c.plan.split, c.probs, c.count, c.nmax, c0, j0,
+        return dpp::launch_leaf_lu(c.plan.dtype, c.plan.pieces, c.probs, c.count, c.nmax, c0, j0,
                                    c.plan.ss, c.s);
     });
 }
@@ -385,8 +387,8 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.info = q.info;
         d.stats = q.stats;
         d.diag = reinterpret_cast<double*>(base_of[(size_t)i]);
-        d.split = plan.split ? reinterpret_cast<uint16_t*>(base_of[(size_t)i] + diag_bytes(q.n))
-                             : nullptr;
+        d.split = plan.pieces ? reinterpret_cast<uint16_t*>(base_of[(size_t)i] + diag_bytes(q.n))
+                              : nullptr;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     bool profiling;

@@ -44,11 +44,14 @@ __device__ __forceinline__ const T* first_source(const DevProb& P, bool first, i
     return first ? static_cast<const T*>(P.K) : static_cast<const T*>(P.A);
 }
 
-// Split-BF16 panel copies of a problem: four planes q = 0: hi(L), 1: lo(L),
-// 2: hi(B), 3: lo(B), entry (r, kk) with r the global row of L (or the global
-// column of the update for B) and kk = k - j0 the column within the current
-// outer panel (ss columns per row, a multiple of 64). For LDL^H, B = L D (the
-// scaled column, W); for LU, B = U^T. Values are bf16 bit patterns.
+// Split-BF16 panel copies of a problem: each factor value x is cut into
+// `np` BF16 pieces (np = 2 or 3), p_0 = bf16(x) and p_i = bf16(x - p_0 - ...
+// - p_{i-1}), so that their sum carries about 8 np significant bits of x. The
+// 2 np planes are q = i: piece i of L, q = np + i: piece i of B, entry (r, kk)
+// with r the global row of L (or the global column of the update for B) and
+// kk = k - j0 the column within the current outer panel (ss columns per row,
+// a multiple of 64). For LDL^H, B = L D (the scaled column, W); for LU,
+// B = U^T. Values are bf16 bit patterns.
 // Each plane is tiled in blocks of 32 rows x 32 columns (2 KiB), row blocks
 // outer, and inside a block by halves of 16 columns: a half holds its 32 rows
 // of 16 values (32 bytes) back to back. So the 16 rows x 32 columns an update
@@ -71,11 +74,11 @@ __host__ __device__ inline int64_t plane_off(int64_t r, int kk, int ss)
 
 // Diagonal block [c0, c0+64) of every problem: decisions, L11/D1 (or L11/U11),
 // and the panel solves for the rows below it (LU: and the columns to its
-// right). With split != 0 also writes the split-BF16 panel copies at outer
-// panel offset j0 with row stride ss.
-hipError_t launch_leaf_ldlh(int dtype, bool split, const DevProb* probs, int nprob, int64_t nmax,
+// right). With pieces = 2 or 3 also writes that many split-BF16 pieces of
+// each panel value (0: none) at outer panel offset j0 with row stride ss.
+hipError_t launch_leaf_ldlh(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
                             int64_t c0, int64_t j0, int ss, hipStream_t s);
-hipError_t launch_leaf_lu(int dtype, bool split, const DevProb* probs, int nprob, int64_t nmax,
+hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
                           int64_t c0, int64_t j0, int ss, hipStream_t s);
 
 // Schur-complement update of rows [base, n) x cols [base, min(base+ncols, n))
@@ -95,9 +98,11 @@ inline Region trailing_region(int64_t base, int64_t ncols)
 
 hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
                              Region rg, int64_t k0, int kw, hipStream_t s);
-hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int nprob,
-                                int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
-                                hipStream_t s);
+// Split-BF16 form: the products of the `pieces` (2 or 3) BF16 pieces of L and
+// B whose orders sum to at most pieces - 1 (3 or 6 MFMA products).
+hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs, int nprob,
+                               int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
+                               hipStream_t s);
 
 // loglik (fixed-order sum of ln|piv|) and info, one workgroup per problem.
 hipError_t launch_finalize(const DevProb* probs, int nprob, hipStream_t s);

@@ -133,13 +133,43 @@ __device__ __forceinline__ void buf_store<float>(double v, __amdgpu_buffer_rsrc_
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), r, voff, soff, 0);
 }
 
-// hi/lo BF16 split of one value: hi = bf16(x), lo = bf16(x - hi), so that
-// hi + lo carries about 16 significant bits of x.
-__device__ __forceinline__ void split_bf16(double x, uint16_t& hi, uint16_t& lo)
+// BF16 pieces of one value: p_0 = bf16(x), p_i = bf16(x - p_0 - ... -
+// p_{i-1}) (each remainder exact in FP64, rounded through FP32), so that the
+// NPC pieces carry about 8 NPC significant bits of x.
+template <int NPC>
+__device__ __forceinline__ void split_pieces(double x, uint32_t (&p)[NPC])
 {
-    const uint32_t xh = bf16_bits((float)x);
-    hi = (uint16_t)xh;
-    lo = (uint16_t)bf16_bits((float)(x - (double)bf16_value(xh)));
+    double r = x;
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+        p[i] = bf16_bits((float)r);
+        if (i + 1 < NPC) r -= (double)bf16_value(p[i]);
+    }
+}
+
+// Writes the NPC pieces of 8 consecutive panel values v[0..7] of row r,
+// columns kk .. kk+7 of the outer panel (kk a multiple of 8), to the planes
+// q0 .. q0 + NPC - 1: one 16-byte store per plane.
+template <int NPC>
+__device__ __forceinline__ void store_pieces8(uint16_t* base, int64_t n, int ss, int q0, int64_t r,
+                                              int kk, const double (&v)[8])
+{
+    if constexpr (NPC > 0) {
+        uint32_t w[NPC][4];
+#pragma unroll
+        for (int p2 = 0; p2 < 4; ++p2) {
+            uint32_t a[NPC], b[NPC];
+            split_pieces<NPC>(v[2 * p2], a);
+            split_pieces<NPC>(v[2 * p2 + 1], b);
+#pragma unroll
+            for (int i = 0; i < NPC; ++i) w[i][p2] = a[i] | (b[i] << 16);
+        }
+        const int64_t o = plane_off(r, kk, ss);
+#pragma unroll
+        for (int i = 0; i < NPC; ++i)
+            *reinterpret_cast<uint4*>(split_plane(base, n, ss, q0 + i) + o) =
+                make_uint4(w[i][0], w[i][1], w[i][2], w[i][3]);
+    }
 }
 
 // ------------------------------------------------------------ panel solves

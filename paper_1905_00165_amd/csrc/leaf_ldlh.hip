@@ -25,7 +25,7 @@ using namespace leaf;
 // The four inverses L_bb^{-1} (unit lower triangular) are formed once per
 // workgroup by forward substitution, one column per lane.
 // Then L21 = W D1^{-1}; A receives L21, the split planes W and L21.
-template <typename T, bool SPLIT>
+template <typename T, int NPC>
 __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restrict__ probs, int64_t c0,
                                                int64_t j0, int ss, int gpw)
 {
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
         solve_group(sL, sI, cur, x, q, i16);  // W = A21 L11^{-T}
         // x[b][e] = W[row][16b + 4e + q], row = wrow0 + 16g + i16.
         const int64_t r = wrow0 + 16 * g + i16;
-        if constexpr (SPLIT) {
+        if constexpr (NPC > 0) {
             // The split planes are row-major: stage W through LDS so that each
             // lane writes 16-byte pieces of one row (lane l: row l/4, columns
             // 8(l%4) + [0, 8) and 32 + 8(l%4) + [0, 8)).
@@ -216,27 +216,15 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
                 const int kk = (int)(c0 - j0) + tc;
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
-                    uint32_t wh[4], wl[4], lh[4], ll[4];
+                    double wv[8], lv[8];
 #pragma unroll
-                    for (int p2 = 0; p2 < 4; ++p2) {
-                        uint16_t h0, l0, h1, l1, a0, b0, a1, b1;
-                        const int col = 32 * half + tc + 2 * p2;
-                        const double w0 = tile[tr * kTilePitch + col];
-                        const double w1 = tile[tr * kTilePitch + col + 1];
-                        split_bf16(w0, h0, l0);
-                        split_bf16(w1, h1, l1);
-                        split_bf16(w0 * sR[col], a0, b0);
-                        split_bf16(w1 * sR[col + 1], a1, b1);
-                        wh[p2] = h0 | ((uint32_t)h1 << 16);
-                        wl[p2] = l0 | ((uint32_t)l1 << 16);
-                        lh[p2] = a0 | ((uint32_t)a1 << 16);
-                        ll[p2] = b0 | ((uint32_t)b1 << 16);
+                    for (int c = 0; c < 8; ++c) {
+                        const int col = 32 * half + tc + c;
+                        wv[c] = tile[tr * kTilePitch + col];
+                        lv[c] = wv[c] * sR[col];
                     }
-                    const int64_t o = plane_off(rr, kk + 32 * half, ss);
-                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 2) + o) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
-                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 3) + o) = make_uint4(wl[0], wl[1], wl[2], wl[3]);
-                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 0) + o) = make_uint4(lh[0], lh[1], lh[2], lh[3]);
-                    *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, 1) + o) = make_uint4(ll[0], ll[1], ll[2], ll[3]);
+                    store_pieces8<NPC>(P.split, n, ss, NPC, rr, kk + 32 * half, wv);  // W = L D
+                    store_pieces8<NPC>(P.split, n, ss, 0, rr, kk + 32 * half, lv);    // L
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -253,24 +241,26 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
 }
 
 template <typename T>
-hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, int64_t c0,
+hipError_t launch_t(int pieces, const DevProb* probs, int nprob, int64_t nmax, int64_t c0,
                     int64_t j0, int ss, hipStream_t s)
 {
     int gx = 1;
     const int gpw = groups_per_wave(nmax - c0 - L, nprob, 2, &gx);  // two workgroups per CU
     dim3 grid(gx, nprob), block(kThreads);
-    if (split) hipLaunchKernelGGL((leaf_ldlh<T, true>), grid, block, 0, s, probs, c0, j0, ss, gpw);
-    else hipLaunchKernelGGL((leaf_ldlh<T, false>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    if (pieces == 3) hipLaunchKernelGGL((leaf_ldlh<T, 3>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    else if (pieces == 2) hipLaunchKernelGGL((leaf_ldlh<T, 2>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    else hipLaunchKernelGGL((leaf_ldlh<T, 0>), grid, block, 0, s, probs, c0, j0, ss, gpw);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_leaf_ldlh(int dtype, bool split, const DevProb* probs, int nprob, int64_t nmax,
-                      int64_t c0, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_leaf_ldlh(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
+                            int64_t c0, int64_t j0, int ss, hipStream_t s)
 {
-    if (dtype == 0) return launch_t<double>(split, probs, nprob, nmax, c0, j0, ss, s);
-    return launch_t<float>(split, probs, nprob, nmax, c0, j0, ss, s);
+    if (pieces != 0 && pieces != 2 && pieces != 3) return hipErrorInvalidValue;
+    if (dtype == 0) return launch_t<double>(pieces, probs, nprob, nmax, c0, j0, ss, s);
+    return launch_t<float>(pieces, probs, nprob, nmax, c0, j0, ss, s);
 }
 
 }  // namespace dpp

@@ -21,7 +21,8 @@ using namespace leaf;
 //     column U12^T L11^T = A12^T: X = A12^T with T = L11 (unit lower).
 // The row panel's columns are contiguous in memory; they pass through the
 // wavefront's LDS tile so that loads and stores stay coalesced. A receives L21
-// and U12; the split planes, hi/lo of L21 by row and of U12^T by column.
+// and U12; the split planes, the BF16 pieces of L21 by row and of U12^T by
+// column.
 // Each workgroup takes the same number of rows of the column panel and
 // columns of the row panel (splitting them over separate workgroups measured
 // slower: the chain, repeated per workgroup, dominates).
@@ -35,7 +36,7 @@ using namespace leaf;
 // a launch needs more than one round.
 constexpr int kLP = L + 1;
 
-template <typename T, bool SPLIT>
+template <typename T, int NPC>
 __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
                                              int64_t j0, int ss, int gpw)
 {
@@ -152,28 +153,17 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict
 
     // Split planes from the tile: lane l writes row l/4 (of the group),
     // entries 8(l%4) + [0, 8) and 32 + 8(l%4) + [0, 8), 16-byte pieces.
-    auto planes_from_tile = [&](int64_t gr0, int plane_hi) {
+    auto planes_from_tile = [&](int64_t gr0, int q0) {
         const int tr = lane >> 2, tc = 8 * (lane & 3);
         const int64_t rr = gr0 + tr;
         if (rr >= n) return;
         const int kk = (int)(c0 - j0) + tc;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
-            uint32_t h[4], lo[4];
+            double v[8];
 #pragma unroll
-            for (int p2 = 0; p2 < 4; ++p2) {
-                uint16_t h0, l0, h1, l1;
-                const int col = 32 * half + tc + 2 * p2;
-                split_bf16(tile[tr * kTilePitch + col], h0, l0);
-                split_bf16(tile[tr * kTilePitch + col + 1], h1, l1);
-                h[p2] = h0 | ((uint32_t)h1 << 16);
-                lo[p2] = l0 | ((uint32_t)l1 << 16);
-            }
-            const int64_t o = plane_off(rr, kk + 32 * half, ss);
-            *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, plane_hi) + o) =
-                make_uint4(h[0], h[1], h[2], h[3]);
-            *reinterpret_cast<uint4*>(split_plane(P.split, n, ss, plane_hi + 1) + o) =
-                make_uint4(lo[0], lo[1], lo[2], lo[3]);
+            for (int c = 0; c < 8; ++c) v[c] = tile[tr * kTilePitch + 32 * half + tc + c];
+            store_pieces8<NPC>(P.split, n, ss, q0, rr, kk + 32 * half, v);
         }
     };
 
@@ -211,7 +201,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict
 #pragma unroll
                     for (int e = 0; e < 4; ++e) buf_store<T>(x[b][e], rs, v, (16 * b + 4 * e) * cstride);
             }
-            if constexpr (SPLIT) {
+            if constexpr (NPC > 0) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -268,14 +258,14 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict
 #pragma unroll
                 for (int k = 0; k < 16; ++k) dst[k] = (T)tile[tcl * kTilePitch + tk + k];
             }
-            if constexpr (SPLIT) planes_from_tile(w0 + 16 * g, 2);
+            if constexpr (NPC > 0) planes_from_tile(w0 + 16 * g, NPC);
             __builtin_amdgcn_wave_barrier();
         }
     }
 }
 
 template <typename T>
-hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, int64_t c0,
+hipError_t launch_t(int pieces, const DevProb* probs, int nprob, int64_t nmax, int64_t c0,
                     int64_t j0, int ss, hipStream_t s)
 {
     int gx = 1;
@@ -283,18 +273,20 @@ hipError_t launch_t(bool split, const DevProb* probs, int nprob, int64_t nmax, i
     // wavefront, twice the redundant chains) measured slower.
     const int gpw = groups_per_wave(nmax - c0 - L, nprob, 1, &gx);
     dim3 grid(gx, nprob), block(kThreads);
-    if (split) hipLaunchKernelGGL((leaf_lu<T, true>), grid, block, 0, s, probs, c0, j0, ss, gpw);
-    else hipLaunchKernelGGL((leaf_lu<T, false>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    if (pieces == 3) hipLaunchKernelGGL((leaf_lu<T, 3>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    else if (pieces == 2) hipLaunchKernelGGL((leaf_lu<T, 2>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    else hipLaunchKernelGGL((leaf_lu<T, 0>), grid, block, 0, s, probs, c0, j0, ss, gpw);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_leaf_lu(int dtype, bool split, const DevProb* probs, int nprob, int64_t nmax,
+hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
                           int64_t c0, int64_t j0, int ss, hipStream_t s)
 {
-    if (dtype == 0) return launch_t<double>(split, probs, nprob, nmax, c0, j0, ss, s);
-    return launch_t<float>(split, probs, nprob, nmax, c0, j0, ss, s);
+    if (pieces != 0 && pieces != 2 && pieces != 3) return hipErrorInvalidValue;
+    if (dtype == 0) return launch_t<double>(pieces, probs, nprob, nmax, c0, j0, ss, s);
+    return launch_t<float>(pieces, probs, nprob, nmax, c0, j0, ss, s);
 }
 
 }  // namespace dpp

@@ -1,28 +1,34 @@
 // Split-BF16 Schur-complement update of the blocked DPP sampler on gfx950 MFMA.
 //
 // Same update as update_f64.hip (the outer-product update of the blocked
-// factorization, Sec. 3), with each factor x split as hi + lo, hi = bf16(x),
-// lo = bf16(x - hi), and the product formed as hi*hi' + hi*lo' + lo*hi' on
-// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the lo*lo' term, about
-// 2^-16 of the product, is dropped). The FP32 sum is subtracted from the
-// stored value in FP64 and rounded to the storage type.
+// factorization, Sec. 3), with each factor value x cut into NP BF16 pieces
+// p_0 = bf16(x), p_i = bf16(x - p_0 - ... - p_{i-1}) (dpp_internal.h), and
+// the product formed from the pairs of pieces whose orders sum to at most
+// NP - 1 on v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
+//   NP = 2 (update_bf16x3): hi*hi' + hi*lo' + lo*hi'; the dropped lo*lo' and
+//     the pieces' rounding leave about 2^-16 of each product;
+//   NP = 3 (update_bf16x6): p0*p0' + p0*p1' + p1*p0' + p0*p2' + p2*p0' +
+//     p1*p1'; about 2^-24 of each product is left, the order of the FP32
+//     accumulation itself.
+// The FP32 sum is subtracted from the stored value in FP64 and rounded to the
+// storage type.
 //
 // Operands come from the split copies the diagonal-block kernel writes while it
 // solves the panel, tiled so that the rows one stage copies are contiguous
 // (plane_off in dpp_internal.h); 16 bytes are the 8 consecutive k one MFMA
 // lane holds:
-//   rows of C: hi/lo of L;  cols of C: hi/lo of W = L D (LDL^H) or of U^T (LU).
+//   rows of C: pieces of L;  cols of C: pieces of W = L D (LDL^H) or of U^T (LU).
 //
 // Tiling (template Shape): a workgroup owns a TM x TN tile of C split over
 // WR x WC wavefronts, each owning RB x CB blocks of 32x32 (wide shape:
-// 256x256 on 8 wavefronts of 128x64, so each 16-k step reads 12 fragments
-// from LDS and issues 24 MFMAs per wavefront; narrower shapes serve the
-// narrow updates inside a panel). K advances KC (16 or 32) at a time through
-// NST LDS stages holding the four operand planes, NST - 1 of them in flight
-// while one is multiplied, one barrier per stage. Global -> LDS copies use the
-// gfx950 direct-to-LDS loads (global_load_lds_dwordx4), each instruction
-// writing 1 KiB. LDS rows are KC * 2 bytes with their 16-byte segments
-// XOR-swizzled by row (swz below).
+// 256x256 on 8 wavefronts of 128x64, so each 16-k step reads NP * 6
+// fragments from LDS and issues 8 MFMAs per product term per wavefront;
+// narrower shapes serve the narrow updates inside a panel). K advances KC (16
+// or 32) at a time through NST LDS stages holding the 2 NP operand planes,
+// NST - 1 of them in flight while one is multiplied, one barrier per stage.
+// Global -> LDS copies use the gfx950 direct-to-LDS loads
+// (global_load_lds_dwordx4), each instruction writing 1 KiB. LDS rows are
+// KC * 2 bytes with their 16-byte segments XOR-swizzled by row (swz below).
 // The MFMA takes the column operand first, so each lane's accumulators map to
 // one row of C and lanes 0-31 cover 32 consecutive rows of a column: the
 // read-modify-write of column-major C is coalesced. Operand rows past the end
@@ -34,6 +40,7 @@
 // the ~32 tiles an XCD runs at once form an 8x4 block that shares 8 row panels
 // and 4 column panels in that XCD's L2.
 #include <atomic>
+#include <type_traits>
 
 #include "dpp_internal.h"
 
@@ -49,33 +56,59 @@ constexpr int kKAlign = 32;        // every update's k range is a multiple of th
 constexpr int kGroupCols = 4;      // tile columns per group of the wide order
 
 // TM x TN tile on WR x WC wavefronts; K advances KC at a time through NST LDS
-// stages (NST - 1 of them in flight while one is multiplied).
-template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_, int KC_, int NST_>
+// stages (NST - 1 of them in flight while one is multiplied); NP BF16 pieces
+// per operand value.
+template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_, int KC_, int NST_, int NP_>
 struct Shape {
     static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_;
     static constexpr int MINB = MINB_;  // workgroups per CU the register budget allows
     static constexpr int EP = EP_;      // 32x32 blocks per epilogue round
     static constexpr int KC = KC_, NST = NST_;
+    static constexpr int NP = NP_;                                 // pieces per value
+    static constexpr int NTERM = NP == 2 ? 3 : 6;                  // product terms
     static constexpr int ROWB = KC * 2;                            // bytes per operand row and stage
     static constexpr int KSTEPS = KC / 16;                         // MFMA k steps per stage
     static constexpr int NW = WR * WC, THREADS = 64 * NW;
     static constexpr int RB = TM / (32 * WR), CB = TN / (32 * WC);  // 32x32 blocks per wave
     static constexpr int A_PLANE = TM * ROWB, W_PLANE = TN * ROWB;
-    static constexpr int BUF = 2 * A_PLANE + 2 * W_PLANE;           // Lh, Ll, Wh, Wl
+    static constexpr int BUF = NP * (A_PLANE + W_PLANE);           // pieces of L, then of W
     static constexpr int LDS = NST * BUF;
     static constexpr int PER_WAVE = BUF / 1024 / NW;                // 1 KiB copies per stage
     static constexpr int LPR = ROWB / 16;                           // lanes per row in a copy
-    static constexpr int READS = 2 * (RB + CB);                     // fragments per k step
-    static constexpr int MFMAS = 3 * RB * CB;
+    static constexpr int READS = NP * (RB + CB);                    // fragments per k step
+    static constexpr int MFMAS = NTERM * RB * CB;
+    static_assert(NP == 2 || NP == 3, "two or three pieces");
     static_assert(KC == 16 || KC == 32, "rows of 32 or 64 bytes");
     static_assert(kKAlign % KC == 0, "stages must tile every k range");
     static_assert(BUF % (1024 * NW) == 0, "copies must split evenly over wavefronts");
-    static_assert(KSTEPS == 1 || MFMAS % READS == 0, "interleave needs whole MFMA groups per read");
+    static_assert(A_PLANE % 1024 == 0 && W_PLANE % 1024 == 0, "no copy straddles two planes");
+    static_assert(LDS <= 160 * 1024 / MINB, "LDS of MINB workgroups per CU");
     static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
 };
-using Wide = Shape<256, 256, 2, 4, 1, 1, 16, 4>;
-using Medium = Shape<256, 128, 2, 2, 2, 1, 16, 3>;
-using Narrow = Shape<128, 64, 4, 1, 3, 1, 32, 2>;
+// (L piece, W piece) of product term t: the pairs whose orders sum to at most
+// NP - 1, larger terms first.
+__device__ __forceinline__ constexpr int term_a(int t) { return t == 2 ? 1 : t == 4 ? 2 : t == 5 ? 1 : 0; }
+__device__ __forceinline__ constexpr int term_b(int t) { return t == 1 ? 1 : t == 3 ? 2 : t == 5 ? 1 : 0; }
+
+using Wide3 = Shape<256, 256, 2, 4, 1, 1, 16, 4, 2>;
+using Medium3 = Shape<256, 128, 2, 2, 2, 1, 16, 3, 2>;
+using Narrow3 = Shape<128, 64, 4, 1, 3, 1, 32, 2, 2>;
+using Wide6 = Shape<256, 256, 2, 4, 1, 1, 16, 3, 3>;
+using Medium6 = Shape<256, 128, 2, 2, 1, 1, 16, 3, 3>;
+using Narrow6 = Shape<128, 64, 4, 1, 2, 1, 32, 2, 3>;
+
+// MFMAs spread evenly over the READS fragment reads that follow the first
+// group: slot r gets floor((r+1) M / R) - floor(r M / R) MFMAs, then one read.
+template <int M, int R, int r = 0>
+__device__ __forceinline__ void interleave_mfma_reads()
+{
+    if constexpr (r < R) {
+        constexpr int cnt = (r + 1) * M / R - r * M / R;
+        if constexpr (cnt > 0) __builtin_amdgcn_sched_group_barrier(0x008, cnt, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                           // DS read
+        interleave_mfma_reads<M, R, r + 1>();
+    }
+}
 
 // XOR swizzle of the 16-byte segments of LDS row r. A fragment read (lane l:
 // row l % 32, one segment) is served 16 lanes at a time, 256 bytes over the
@@ -192,9 +225,8 @@ __device__ __forceinline__ bool grouped_tile(int64_t t, int64_t NR, int64_t NC, 
 }
 
 template <typename T, bool HERM, class S>
-__global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevProb* __restrict__ probs,
-                                                               Region rg, int64_t k0, int kw,
-                                                               int64_t j0, int ss)
+__device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, Region rg, int64_t k0,
+                                            int kw, int64_t j0, int ss, unsigned char* lds)
 {
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
@@ -223,8 +255,6 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     int64_t lds_;  // leading dimension of the source C is read from (K when k0 == 0)
     const T* __restrict__ Csrc = first_source<T>(P, k0 == 0, lds_);
 
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -236,7 +266,7 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     const int kk0 = (int)(k0 - j0);
 
     // Direct-to-LDS copies. Copy i of a stage writes bytes [1024 i, 1024 i + 1024)
-    // of the buffer (planes Lh, Ll, Wh, Wl back to back): 1024 / ROWB rows of
+    // of the buffer (the pieces of L, then of W, back to back): 1024 / ROWB rows of
     // one plane. Lane l supplies row l / LPR of that block, physical segment
     // l % LPR, i.e. logical segment (l % LPR) ^ swz(row); the block starts at a
     // multiple of 16 rows, so swz depends on l only.
@@ -248,16 +278,16 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
             const int i = wave * S::PER_WAVE + q;  // copy index, uniform
             const int off = i * 1024;
             int plane, row0;
-            if (off < 2 * S::A_PLANE) {
+            if (off < S::NP * S::A_PLANE) {
                 plane = off / S::A_PLANE;
                 row0 = (off % S::A_PLANE) / S::ROWB;
             } else {
-                const int o2 = off - 2 * S::A_PLANE;
-                plane = 2 + o2 / S::W_PLANE;
+                const int o2 = off - S::NP * S::A_PLANE;
+                plane = S::NP + o2 / S::W_PLANE;
                 row0 = (o2 % S::W_PLANE) / S::ROWB;
             }
-            const int64_t first = plane < 2 ? rowT0 : colT0;
-            const int64_t last = (plane < 2 ? rEnd : colEnd) - 1;  // rows past it: reuse it
+            const int64_t first = plane < S::NP ? rowT0 : colT0;
+            const int64_t last = (plane < S::NP ? rEnd : colEnd) - 1;  // rows past it: reuse it
             int64_t g = first + row0 + rl;
             g = g < last ? g : last;
             __builtin_amdgcn_global_load_lds(
@@ -380,46 +410,50 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
         // from moving LDS accesses across the barrier.
         asm volatile("s_barrier" ::: "memory");
         if (st + S::NST - 1 < nstages) issue_stage((st + S::NST - 1) * S::KC, (st + S::NST - 1) % S::NST);
-        else if (st == nstages - 1) c_load(0, cva);  // first C round in flight during the last stage
+        // First C round in flight during the last stage (with three pieces
+        // the fragments leave no registers for it: loaded after the loop).
+        else if (S::NP == 2 && st == nstages - 1) c_load(0, cva);
         const unsigned char* B0 = lds + buf * S::BUF;
-        bf8 lh[S::KSTEPS][S::RB], ll[S::KSTEPS][S::RB], wh[S::KSTEPS][S::CB], wl[S::KSTEPS][S::CB];
-        // Fragments in the order the MFMAs below consume them.
-        auto read_frags = [&](int ks) {
+        bf8 lp[S::NP][S::KSTEPS][S::RB], wp[S::NP][S::KSTEPS][S::CB];
+        auto read_l = [&](int p, int ks) {
             const int seg = ks * 2 + (lane >> 5);  // 8 k values per lane
 #pragma unroll
             for (int b = 0; b < S::RB; ++b) {
                 const int ra = wr * (S::TM / S::WR) + b * 32 + (lane & 31);
-                lh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + lds_off<S::ROWB>(ra, seg)));
-            }
-#pragma unroll
-            for (int b = 0; b < S::CB; ++b) {
-                const int rc = wc * (S::TN / S::WC) + b * 32 + (lane & 31);
-                wh[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + lds_off<S::ROWB>(rc, seg)));
-            }
-#pragma unroll
-            for (int b = 0; b < S::CB; ++b) {
-                const int rc = wc * (S::TN / S::WC) + b * 32 + (lane & 31);
-                wl[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + 2 * S::A_PLANE + S::W_PLANE + lds_off<S::ROWB>(rc, seg)));
-            }
-#pragma unroll
-            for (int b = 0; b < S::RB; ++b) {
-                const int ra = wr * (S::TM / S::WR) + b * 32 + (lane & 31);
-                ll[ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + S::A_PLANE + lds_off<S::ROWB>(ra, seg)));
+                lp[p][ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + p * S::A_PLANE + lds_off<S::ROWB>(ra, seg)));
             }
         };
-        // The three products of one accumulator are RB*CB MFMAs apart, so
+        auto read_w = [&](int p, int ks) {
+            const int seg = ks * 2 + (lane >> 5);
+#pragma unroll
+            for (int b = 0; b < S::CB; ++b) {
+                const int rc = wc * (S::TN / S::WC) + b * 32 + (lane & 31);
+                wp[p][ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + S::NP * S::A_PLANE + p * S::W_PLANE + lds_off<S::ROWB>(rc, seg)));
+            }
+        };
+        // Fragments in the order the MFMAs below consume them: L0, W0, W1, L1
+        // (and W2, L2 with three pieces).
+        auto read_frags = [&](int ks) {
+            read_l(0, ks);
+            read_w(0, ks);
+            read_w(1, ks);
+            read_l(1, ks);
+            if constexpr (S::NP == 3) {
+                read_w(2, ks);
+                read_l(2, ks);
+            }
+        };
+        // The products of one accumulator are RB*CB MFMAs apart, so
         // consecutive MFMAs never wait on each other's result.
         auto mfmas = [&](int ks) {
 #pragma unroll
-            for (int term = 0; term < 3; ++term)
+            for (int term = 0; term < S::NTERM; ++term)
 #pragma unroll
                 for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
-                    for (int cb = 0; cb < S::CB; ++cb) {
-                        const bf8& w = term == 1 ? wl[ks][cb] : wh[ks][cb];
-                        const bf8& l = term == 2 ? ll[ks][rb] : lh[ks][rb];
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, l, acc[rb][cb], 0, 0, 0);
-                    }
+                    for (int cb = 0; cb < S::CB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], acc[rb][cb], 0, 0, 0);
         };
         if constexpr (S::KSTEPS == 2) {
             read_frags(0);
@@ -428,16 +462,13 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
             mfmas(1);
             // Schedule: k step 0's fragment reads, then its MFMAs with k step
             // 1's reads interleaved evenly, then k step 1's MFMAs.
-            __builtin_amdgcn_sched_group_barrier(0x100, S::READS, 0);            // DS read
-            for (int r = 0; r < S::READS; ++r) {
-                __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS / S::READS, 0);  // MFMA
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                  // DS read
-            }
+            __builtin_amdgcn_sched_group_barrier(0x100, S::READS, 0);  // DS read
+            interleave_mfma_reads<S::MFMAS, S::READS>();
             __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS, 0);
         } else {
             read_frags(0);
             mfmas(0);
-            // Schedule: the fragments of the first product term (hi x hi),
+            // Schedule: the fragments of the first product term (p0 x p0'),
             // then its MFMAs with the remaining fragment reads interleaved.
             constexpr int first = S::RB + S::CB, rest = S::READS - first;
             __builtin_amdgcn_sched_group_barrier(0x100, first, 0);
@@ -460,9 +491,37 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevPr
     for (int r = 0; r < ROUNDS; ++r) {
         double (&cur)[CP][16] = (r & 1) ? cvb : cva;
         double (&nxt)[CP][16] = (r & 1) ? cva : cvb;
+        if (S::NP == 3 && r == 0) c_load(0, cur);
         if (r + 1 < ROUNDS) c_load(r + 1, nxt);
         c_store(r, cur);
     }
+}
+
+// The two product forms as separate kernels, so that profiles tell them apart.
+template <typename T, bool HERM, class S>
+__global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevProb* __restrict__ probs,
+                                                                     Region rg, int64_t k0, int kw,
+                                                                     int64_t j0, int ss)
+{
+    static_assert(S::NP == 2, "three products from two pieces");
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    update_body<T, HERM, S>(probs, rg, k0, kw, j0, ss, lds);
+}
+template <typename T, bool HERM, class S>
+__global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x6(const DevProb* __restrict__ probs,
+                                                                     Region rg, int64_t k0, int kw,
+                                                                     int64_t j0, int ss)
+{
+    static_assert(S::NP == 3, "six products from three pieces");
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    update_body<T, HERM, S>(probs, rg, k0, kw, j0, ss, lds);
+}
+
+template <typename T, bool HERM, class S>
+constexpr auto kernel_of()
+{
+    if constexpr (S::NP == 2) return update_bf16x3<T, HERM, S>;
+    else return update_bf16x6<T, HERM, S>;
 }
 
 template <typename T, bool HERM, class S>
@@ -472,7 +531,7 @@ hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t 
     const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (nc + S::TN - 1) / S::TN;
     const int64_t tiles = (HERM && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
     const unsigned grid_x = (unsigned)((tiles + 7) / 8 * 8);  // XCD remap needs a multiple of 8
-    auto k = update_bf16x3<T, HERM, S>;
+    const auto k = kernel_of<T, HERM, S>();
     // The dynamic-LDS limit is a per-device function attribute: set it once
     // on each device the kernel runs on.
     static std::atomic<uint64_t> attr_set{0};
@@ -490,10 +549,13 @@ hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t 
     return hipGetLastError();
 }
 
-template <typename T, bool HERM>
+template <typename T, bool HERM, int NP>
 hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, Region rg,
                     int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
+    using Narrow = std::conditional_t<NP == 2, Narrow3, Narrow6>;
+    using Medium = std::conditional_t<NP == 2, Medium3, Medium6>;
+    using Wide = std::conditional_t<NP == 2, Wide3, Wide6>;
     // The tile shape follows the width of the updated column range.
     if (nc <= 128)
         return launch_shape<T, HERM, Narrow>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
@@ -502,22 +564,31 @@ hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, 
     return launch_shape<T, HERM, Wide>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
 }
 
+template <int NP>
+hipError_t launch_np(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nrows,
+                     int64_t nc, Region rg, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
+{
+    if (herm) {
+        if (dtype == 0) return launch_t<double, true, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        return launch_t<float, true, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    }
+    if (dtype == 0) return launch_t<double, false, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    return launch_t<float, false, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+}
+
 }  // namespace
 
-hipError_t launch_update_bf16x3(bool herm, int dtype, const DevProb* probs, int nprob,
-                                int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
-                                hipStream_t s)
+hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs, int nprob,
+                               int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
+                               hipStream_t s)
 {
     const int64_t nrows = (rg.r0 + rg.rlen < nmax ? rg.r0 + rg.rlen : nmax) - rg.r0;
     const int64_t nc = (rg.c0 + rg.clen < nmax ? rg.c0 + rg.clen : nmax) - rg.c0;
     if (nrows <= 0 || nc <= 0) return hipSuccess;
     if (kw % kKAlign != 0 || (herm && rg.r0 != rg.c0)) return hipErrorInvalidValue;
-    if (herm) {
-        if (dtype == 0) return launch_t<double, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-        return launch_t<float, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    }
-    if (dtype == 0) return launch_t<double, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    return launch_t<float, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    if (pieces == 2) return launch_np<2>(herm, dtype, probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    if (pieces == 3) return launch_np<3>(herm, dtype, probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace dpp

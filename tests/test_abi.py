@@ -196,3 +196,15 @@ def test_binding_checks_output_buffers_and_streams():
               torch.empty(4, dtype=torch.float64), torch.empty(10, dtype=torch.float64)[::2]):
         with pytest.raises(ValueError):
             B.check_stream(u, 5, dev)
+
+
+def test_six_product_workspace_holds_six_planes():
+    """DPP_PREC_SPLIT_BF16X6 keeps three BF16 pieces of L and of W: six planes
+    where the three-product form keeps four."""
+    f = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_FP64)
+    s3 = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_SPLIT_BF16)
+    s6 = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_SPLIT_BF16X6)
+    planes = 1024 * 1024 * 2   # rows padded to 32, columns to the 64-wide blocks
+    assert s3 - f == 4 * planes and s6 - f == 6 * planes
+    assert B.dpp_workspace_size(True, B.DPP_F64, 1000, 3) == 0   # unknown precision
+

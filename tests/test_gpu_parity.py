@@ -4,7 +4,7 @@ the same seeded inputs and uniform streams, through the C ABI.
 Tolerances (per run):
   FP64 path: pre-decision probabilities |d_gpu - d_oracle| <= 1e-9 and
              |ll_gpu - ll_oracle| <= 1e-9 |ll_oracle|; near-tie threshold 1e-10.
-  split-BF16 path: 1e-4 and near-tie threshold 1e-5.
+  split-BF16 paths (three and six products): 1e-4 and near-tie threshold 1e-5.
   FP32 storage (FP64 updates): 1e-5, threshold 1e-6 (each stored Schur
              complement entry is rounded to FP32, relative 6e-8 per step).
 A mask difference is allowed only as a counted near tie (tests/parity.py).
@@ -34,9 +34,9 @@ def _gpu():
     yield
 
 
-TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5)}
-PRECS = [0, 1]
-PREC_ID = {0: "fp64", 1: "split"}
+TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5), 2: (1e-4, 1e-5)}
+PRECS = [0, 1, 2]
+PREC_ID = {0: "fp64", 1: "split", 2: "split6"}
 
 
 def _run(herm, K, u, prec, dtype=torch.float64):
@@ -484,7 +484,9 @@ def _big_kernel(which):
         if which == "proj6144":
             K = W.projection_kernel(6144, 1536, seed=12, device=DEV)
         else:
-            K = W.hermitian_kernel(8192, seed=21, device=DEV)
+            # row-major storage of the symmetric kernel: its transpose view
+            # is the column-major matrix the calls take
+            K = W.hermitian_kernel(8192, seed=21, device=DEV).contiguous()
         torch.cuda.synchronize()
         _BIG[which] = (K, K.cpu().numpy(), {})
     return _BIG[which]

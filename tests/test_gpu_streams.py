@@ -58,7 +58,7 @@ def _equal(a, b):
 
 
 @pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "split"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
 def test_batch_of_64_equals_single_calls_and_replay(B, prec, herm):
     """The 64-problem batch equals single calls (one problem per size), and a
     graph of it captured on another stream replays that result bit for bit,

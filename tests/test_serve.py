@@ -34,7 +34,7 @@ def test_admit_is_first_come_first_served():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "split"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
 def test_served_results_equal_standalone_and_overlap(prec):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
