@@ -193,6 +193,31 @@ size_t dpp_workspace_size_batched(int hermitian, dpp_dtype dt, const int64_t* ns
                                   dpp_precision prec);
 
 /*
+ * dpp_sample_ldlh_batched_noalloc - dpp_sample_ldlh_batched for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same launch sequence and
+ * kernels, with the workspace taken from a scratch array the library holds
+ * on each device (DPP_NOALLOC_SCRATCH_BYTES, held from the library's load on
+ * that device until the process ends) instead of the caller's `ws`. The caller
+ * still passes every input and output buffer. The call allocates nothing and
+ * results equal dpp_sample_ldlh_batched's bit for bit.
+ *   Returns DPP_ERR_WORKSPACE when the batch needs more than
+ *   DPP_NOALLOC_SCRATCH_BYTES, i.e. when dpp_workspace_size_batched(1, dt,
+ *   ns, count, prec) exceeds it (one problem fits up to n = 131008 on the
+ *   FP64 path, n = 2848 with DPP_PREC_SPLIT_BF16 and n = 2304 with
+ *   DPP_PREC_SPLIT_BF16X6).
+ *   Every call on one device shares that device's scratch, which keeps the
+ *   last call's contents (no call needs it zeroed): calls that may overlap on
+ *   one device (different streams, or different host threads without
+ *   ordering) race on it and must be serialized by the caller.
+ * The first call on a device looks up the scratch's device address (once per
+ * device, with that device current).
+ */
+#define DPP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dpp_status dpp_sample_ldlh_batched_noalloc(const dpp_problem* probs, int64_t count, dpp_dtype dt,
+                                           dpp_precision prec, void* stream);
+
+/*
  * dpp_copy_lower - stage a working copy for dpp_sample_ldlh: copy the lower
  * triangle (with the diagonal) of the n x n column-major matrix src (leading
  * dimension ld_src) into dst (ld_dst). The in-place LDL^H sampler (Sec. 3,

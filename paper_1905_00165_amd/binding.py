@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdpp.so")
 DPP_F64, DPP_F32 = 0, 1
 DPP_PREC_FP64, DPP_PREC_SPLIT_BF16, DPP_PREC_SPLIT_BF16X6 = 0, 1, 2
 DPP_OK = 0
+DPP_NOALLOC_SCRATCH_BYTES = 64 << 20   # include/dpp.h
 _STATUS = {0: "DPP_OK", 1: "DPP_ERR_INVALID_ARG", 2: "DPP_ERR_WORKSPACE", 3: "DPP_ERR_HIP",
            4: "DPP_ERR_UNSUPPORTED"}
 
@@ -68,6 +69,9 @@ def lib() -> ctypes.CDLL:
         f.argtypes = [ctypes.POINTER(dpp_problem), _i64, ctypes.c_int, ctypes.c_int, _vp,
                       ctypes.c_size_t, _vp]
         f.restype = ctypes.c_int
+    L.dpp_sample_ldlh_batched_noalloc.argtypes = [ctypes.POINTER(dpp_problem), _i64, ctypes.c_int,
+                                                  ctypes.c_int, _vp]
+    L.dpp_sample_ldlh_batched_noalloc.restype = ctypes.c_int
     L.dpp_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int]
     L.dpp_workspace_size.restype = ctypes.c_size_t
     L.dpp_workspace_size_batched.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_i64),
@@ -264,7 +268,7 @@ def dpp_sample_lu(A, u, prec=DPP_PREC_FP64, ws=None, out=None):
     return _single("dpp_sample_lu", False, A, u, prec, ws, out)
 
 
-def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None, npivs=None):
+def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None, npivs=None, noalloc=False):
     if len(As) != len(us) or not As:
         raise ValueError("need matching, non-empty lists of matrices and streams")
     if Ks is not None and len(Ks) != len(As):
@@ -298,9 +302,12 @@ def _batched(name, hermitian, As, us, prec, ws, outs, Ks=None, npivs=None):
                                st.data_ptr() if st is not None else None)
         res.append(o)
         ns.append(n)
-    ws = _workspace(ws, dpp_workspace_size_batched(hermitian, dt, ns, prec), dev)
-    st = getattr(lib(), name)(probs, len(As), dt, int(prec), ws.data_ptr(), ws.numel(),
-                              _stream_handle(dev))
+    if noalloc:
+        st = getattr(lib(), name)(probs, len(As), dt, int(prec), _stream_handle(dev))
+    else:
+        ws = _workspace(ws, dpp_workspace_size_batched(hermitian, dt, ns, prec), dev)
+        st = getattr(lib(), name)(probs, len(As), dt, int(prec), ws.data_ptr(), ws.numel(),
+                                  _stream_handle(dev))
     if st != DPP_OK:
         raise DppError(st, name)
     return res
@@ -313,6 +320,16 @@ def dpp_sample_ldlh_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=N
     problem i decides only its first npivs[i] indices (a multiple of 64) and
     leaves the conditional marginal kernel of the rest in A's trailing block."""
     return _batched("dpp_sample_ldlh_batched", True, As, us, prec, ws, outs, Ks, npivs)
+
+
+def dpp_sample_ldlh_batched_noalloc(As, us, prec=DPP_PREC_FP64, outs=None, Ks=None, npivs=None):
+    """dpp_sample_ldlh_batched with the library's own per-device scratch as
+    the workspace (at most DPP_NOALLOC_SCRATCH_BYTES): the library allocates
+    nothing. Outputs not given in `outs` are allocated here, by the caller's
+    side, as for the other calls. Calls that may overlap on one device race
+    on the shared scratch."""
+    return _batched("dpp_sample_ldlh_batched_noalloc", True, As, us, prec, None, outs, Ks, npivs,
+                    noalloc=True)
 
 
 def dpp_sample_lu_batched(As, us, prec=DPP_PREC_FP64, ws=None, outs=None, Ks=None, npivs=None):

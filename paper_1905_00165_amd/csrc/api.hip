@@ -485,9 +485,55 @@ bool lens_args_ok(const dpp_lensemble& q, dpp_dtype dt)
     return l1 <= k0 || k1 <= l0;
 }
 
+// ------------------------------------------------- library-held scratch
+// Workspace of dpp_sample_ldlh_batched_noalloc, for callers that cannot
+// allocate device memory: one file-scope array per device, holding the last
+// call's contents until the process ends. Host code never passes the array's
+// name to a kernel (in host code it names a host-side stand-in); it uses the
+// device address hipGetSymbolAddress returns, looked up once per device with
+// that device current.
+static __device__ __align__(256) unsigned char scratch[DPP_NOALLOC_SCRATCH_BYTES];
+
+dpp_status scratch_address(void** out)
+{
+    static std::mutex mu;
+    static std::vector<void*> addr;  // per device ordinal; nullptr: not looked up yet
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DPP_ERR_HIP;
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)addr.size() <= dev) addr.resize((size_t)dev + 1, nullptr);
+    if (!addr[(size_t)dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DPP_ERR_HIP;
+        addr[(size_t)dev] = p;
+    }
+    *out = addr[(size_t)dev];
+    return DPP_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+dpp_status dpp_sample_ldlh_batched_noalloc(const dpp_problem* probs, int64_t count, dpp_dtype dt,
+                                           dpp_precision prec, void* stream)
+{
+    if (!probs || count < 1 || count > 65535 || !valid_enums(dt, prec)) return DPP_ERR_INVALID_ARG;
+    std::vector<int64_t> ns((size_t)count);
+    for (int64_t i = 0; i < count; ++i) ns[(size_t)i] = probs[i].n;
+    const size_t need = workspace_batched(true, dt, ns.data(), count, prec);
+    if (need == 0) return DPP_ERR_INVALID_ARG;
+    if (need > (size_t)DPP_NOALLOC_SCRATCH_BYTES) return DPP_ERR_WORKSPACE;
+    const dpp_status dev = device_ok();
+    if (dev != DPP_OK) return dev;
+    void* ws = nullptr;
+    const dpp_status st = scratch_address(&ws);
+    if (st != DPP_OK) return st;
+    // Nothing in the workspace needs to start at zero: every launch writes
+    // what a later launch of the same call reads.
+    return run(true, probs, count, dt, prec, ws, (size_t)DPP_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 
 size_t dpp_lensemble_workspace_size(const int64_t* ns, int64_t count)
 {

@@ -208,3 +208,21 @@ def test_six_product_workspace_holds_six_planes():
     assert s3 - f == 4 * planes and s6 - f == 6 * planes
     assert B.dpp_workspace_size(True, B.DPP_F64, 1000, 3) == 0   # unknown precision
 
+
+def test_noalloc_argument_errors_return_before_any_launch():
+    """The no-allocation entry point checks its arguments, and that the batch
+    fits the library's scratch, before touching the device."""
+    f = B.lib().dpp_sample_ldlh_batched_noalloc
+    p = ctypes.c_void_p(0x1000)
+    ok = B.dpp_problem(p, 100, 100, p, p, p, p, p, None, 0, 0, None)
+    arr = (B.dpp_problem * 1)(ok)
+    assert f(None, 1, 0, 0, None) == 1                 # no descriptors
+    assert f(arr, 0, 0, 0, None) == 1                  # count < 1
+    assert f(arr, 1, 0, 7, None) == 1                  # unknown precision
+    assert f(arr, 1, 5, 0, None) == 1                  # unknown dtype
+    bad = (B.dpp_problem * 1)(B.dpp_problem(p, 0, 100, p, p, p, p, p, None, 0, 0, None))
+    assert f(bad, 1, 0, 0, None) == 1                  # n < 1
+    # one six-product problem of n = 3072 needs more than the 64 MiB scratch
+    big = (B.dpp_problem * 1)(B.dpp_problem(p, 3072, 3072, p, p, p, p, p, None, 0, 0, None))
+    assert B.dpp_workspace_size(True, B.DPP_F64, 3072, 2) > B.DPP_NOALLOC_SCRATCH_BYTES
+    assert f(big, 1, 0, 2, None) == 2                  # DPP_ERR_WORKSPACE
