@@ -54,8 +54,19 @@ typedef enum {
 
 /* Storage type of A. The pivots, the keep/reject test and the log-likelihood
    are always computed in FP64; with DPP_F32 the Schur complements are rounded
-   to FP32 when they are stored back. */
-typedef enum { DPP_F64 = 0, DPP_F32 = 1 } dpp_dtype;
+   to FP32 when they are stored back.
+   DPP_C128: complex entries, two FP64 parts (real, imaginary) each, leading
+   dimensions counted in complex entries (at most 2^19). For the complex
+   kernels of the paper (Sec. 1 domino tilings, Sec. 3 dense complex LU), a
+   conditional inclusion probability is real: index j is kept iff u_j < d_j
+   with d_j the real part of the current diagonal entry, and the pivot loses 1
+   on a rejection (its imaginary part, nonzero only for LU, is kept). The
+   Hermitian sampler forms K - 1_{Y^c} = L D L^H with D real; the LU sampler
+   scales by the whole complex pivot. Outputs (mask, pivots = the real d'_j,
+   loglik = sum ln|d'_j|, info) are as for real kernels; npiv (batched calls)
+   must then be a multiple of 32. Not accepted by dpp_copy_lower and the
+   L-ensemble conversion. */
+typedef enum { DPP_F64 = 0, DPP_F32 = 1, DPP_C128 = 2 } dpp_dtype;
 
 /* Arithmetic of the Schur-complement (trailing) updates.
    DPP_PREC_FP64: FP64 MFMA products, FP64 accumulation.
@@ -143,7 +154,7 @@ size_t dpp_workspace_size(int hermitian, dpp_dtype dt, int64_t n, dpp_precision 
              remaining indices conditioned on those decisions: the Schur
              complement of K - 1_{Y^c} restricted to the decided indices
              (Props. 3-5). Sampling that block with its own call continues the
-             same chain. Argument error otherwise.
+             same chain. Argument error otherwise. (DPP_C128: a multiple of 32.)
      stats   out, optional (NULL: not computed), 3 FP64 diagnostics of the
              decisions over the decided indices j, with d_j the pre-decision
              probability (recovered as d'_j, or d'_j + 1 for a rejection):

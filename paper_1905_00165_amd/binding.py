@@ -14,7 +14,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdpp.so")
 
-DPP_F64, DPP_F32 = 0, 1
+DPP_F64, DPP_F32, DPP_C128 = 0, 1, 2
 DPP_PREC_FP64, DPP_PREC_SPLIT_BF16, DPP_PREC_SPLIT_BF16X6 = 0, 1, 2
 DPP_OK = 0
 DPP_NOALLOC_SCRATCH_BYTES = 64 << 20   # include/dpp.h
@@ -162,7 +162,9 @@ def _dtype_code(A) -> int:
         return DPP_F64
     if A.dtype == torch.float32:
         return DPP_F32
-    raise TypeError(f"A must be float64 or float32, got {A.dtype}")
+    if A.dtype == torch.complex128:
+        return DPP_C128
+    raise TypeError(f"A must be float64, float32 or complex128, got {A.dtype}")
 
 
 def _check_matrix(A):

@@ -39,17 +39,21 @@ using dpp::kLeaf;
 
 struct Plan {
     bool herm;
-    int dtype;   // 0 FP64 storage, 1 FP32 storage
+    int dtype;   // 0 FP64 storage, 1 FP32 storage, 2 complex (FP64 parts)
+    bool cplx;   // complex: blocks of kLeafC complex columns, real forms in the updates
+    int leaf;    // diagonal-block width (kLeaf, or kLeafC for complex)
     int pieces;  // split-BF16 updates: BF16 pieces per value (2 or 3), 0: FP64 updates
-    int B0;      // outer panel width (kLeaf times a power of two)
-    int ss;      // row stride of the split panel copies (elements)
+    int B0;      // outer panel width (leaf times a power of two)
+    int ss;      // row stride of the split panel copies (real k columns)
 };
 
 Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
 {
     Plan p;
     p.herm = herm;
-    p.dtype = (dt == DPP_F32) ? 1 : 0;
+    p.dtype = dt == DPP_F32 ? 1 : dt == DPP_C128 ? 2 : 0;
+    p.cplx = dt == DPP_C128;
+    p.leaf = p.cplx ? dpp::kLeafC : kLeaf;
     p.pieces = prec == DPP_PREC_SPLIT_BF16 ? 2 : prec == DPP_PREC_SPLIT_BF16X6 ? 3 : 0;
     // Outer panel width: each trailing update reads and writes the trailing
     // matrix once, so its HBM traffic per sample is ~ 8 n^3 / (3 B0) bytes for
@@ -57,42 +61,48 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     // LU's rank-64 steps inside a panel touch ~ (n - j0) B0 / 2 entries of the
     // panel and ~ (n - j1) B0 / 2 of the rows of U to its right, against
     // (n - j1)^2 per trailing update; B0 = 512 balances them at n = 8192.
+    // A complex column is two real columns of the products' real forms, so
+    // complex panels are half as wide for the same real panel width.
     if (herm) p.B0 = p.pieces ? 4096 : 2048;
     else p.B0 = 512;
+    if (p.cplx) p.B0 /= 2;
     // The split copies hold the columns of one outer panel, at most B0 and no
     // more than the largest problem has (rounded to whole blocks), so small
     // batched problems keep small copies. B0 itself (the blocking) does not
     // depend on the sizes in the batch.
-    const int64_t cap = (nmax + kLeaf - 1) / kLeaf * kLeaf;
-    p.ss = p.B0 < cap ? p.B0 : (int)cap;
+    const int64_t cap = (nmax + p.leaf - 1) / p.leaf * p.leaf;
+    p.ss = (p.B0 < cap ? p.B0 : (int)cap) * (p.cplx ? 2 : 1);
     return p;
 }
 
 // Largest leading dimension: the kernels address a column strip (up to 256
-// columns of A) with 32-bit byte offsets.
+// columns of A) with 32-bit byte offsets; complex entries take twice the bytes.
 constexpr int64_t kMaxLda = (int64_t)1 << 20;
+int64_t max_lda(dpp_dtype dt) { return dt == DPP_C128 ? kMaxLda / 2 : kMaxLda; }
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Planes of L have one row per real row of the Schur complement (two per
+// complex row), planes of B one per column.
 size_t split_bytes(const Plan& p, int64_t n)
 {
-    return p.pieces ? align_up((size_t)(2 * p.pieces) * (size_t)dpp::plane_rows(n) * (size_t)p.ss *
-                               sizeof(uint16_t))
-                    : 0;
+    const size_t rows = (size_t)dpp::plane_rows(p.cplx ? 2 * n : n) + (size_t)dpp::plane_rows(n);
+    return p.pieces ? align_up((size_t)p.pieces * rows * (size_t)p.ss * sizeof(uint16_t)) : 0;
 }
-size_t diag_bytes(int64_t n)
+size_t diag_bytes(const Plan& p, int64_t n)
 {
-    return align_up((size_t)((n + kLeaf - 1) / kLeaf) * kLeaf * kLeaf * sizeof(double));
+    const size_t elt = p.cplx ? 2 * sizeof(double) : sizeof(double);
+    return align_up((size_t)((n + p.leaf - 1) / p.leaf) * p.leaf * p.leaf * elt);
 }
 // Per-problem workspace: [diagonal-block strip][split copies].
-size_t problem_bytes(const Plan& p, int64_t n) { return diag_bytes(n) + split_bytes(p, n); }
+size_t problem_bytes(const Plan& p, int64_t n) { return diag_bytes(p, n) + split_bytes(p, n); }
 // Workspace layout: [descriptors][per problem: diagonal strip, split copies].
 size_t desc_bytes(int64_t count) { return align_up((size_t)count * sizeof(DevProb)); }
 
 bool valid_enums(dpp_dtype dt, dpp_precision prec)
 {
-    return (dt == DPP_F64 || dt == DPP_F32) &&
+    return (dt == DPP_F64 || dt == DPP_F32 || dt == DPP_C128) &&
            (prec == DPP_PREC_FP64 || prec == DPP_PREC_SPLIT_BF16 || prec == DPP_PREC_SPLIT_BF16X6);
 }
 
@@ -116,12 +126,13 @@ dpp_status device_ok()
 // ------------------------------------------------------------------ profiling
 // Kernel families whose launches the profiler tells apart.
 enum KernelId {
-    K_LEAF_LDLH, K_LEAF_LU, K_UPDATE_F64, K_UPDATE_BF16X3, K_UPDATE_BF16X6, K_STORE_DIAG,
-    K_FINALIZE, K_DESCS, K_COUNT
+    K_LEAF_LDLH, K_LEAF_LU, K_LEAF_ZLDLH, K_LEAF_ZLU, K_UPDATE_F64, K_UPDATE_BF16X3,
+    K_UPDATE_BF16X6, K_STORE_DIAG, K_FINALIZE, K_DESCS, K_COUNT
 };
-const char* const kKernelNames[K_COUNT] = {"leaf_ldlh",     "leaf_lu",    "update_f64",
-                                           "update_bf16x3", "update_bf16x6", "store_diag",
-                                           "finalize",      "store_descs"};
+const char* const kKernelNames[K_COUNT] = {"leaf_ldlh",     "leaf_lu",       "leaf_zldlh",
+                                           "leaf_zlu",      "update_f64",    "update_bf16x3",
+                                           "update_bf16x6", "store_diag",    "finalize",
+                                           "store_descs"};
 
 struct ProfRecord {
     int id;
@@ -193,30 +204,38 @@ dpp_status timed(const Ctx& c, int id, double flops, double bytes, F&& launch)
 void update_work(const Ctx& c, const dpp::Region& rg, int kw, double& flops, double& bytes)
 {
     flops = bytes = 0.0;
-    const double elt = c.plan.dtype == 0 ? 8.0 : 4.0;
-    const double opnd = c.plan.pieces ? 2.0 * c.plan.pieces : elt;  // bf16 pieces, or one stored value
+    // Complex: four real products per complex one; entries of 16 bytes.
+    const double cw = c.plan.cplx ? 4.0 : 1.0;
+    const double elt = c.plan.dtype == 0 ? 8.0 : c.plan.dtype == 2 ? 16.0 : 4.0;
+    // Operand bytes per row and k: BF16 pieces of L' (two real rows of two
+    // real k per complex entry) and W' (one row of two), or the stored values.
+    const double opnd_l = c.plan.pieces ? 2.0 * c.plan.pieces * (c.plan.cplx ? 4.0 : 1.0) : elt;
+    const double opnd_w = c.plan.pieces ? 2.0 * c.plan.pieces * (c.plan.cplx ? 2.0 : 1.0) : elt;
     for (int64_t n : *c.ns) {
         const int64_t nr = (rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n) - rg.r0;
         const int64_t nc = (rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n) - rg.c0;
         if (nr <= 0 || nc <= 0) continue;
         const double e = c.plan.herm ? (double)nc * nr - (double)nc * (nc - 1) / 2.0
                                      : (double)nr * nc;
-        flops += 2.0 * e * kw;
-        bytes += 2.0 * e * elt + (double)(nr + nc) * kw * opnd;
+        flops += 2.0 * e * kw * cw;
+        bytes += 2.0 * e * elt + ((double)nr * opnd_l + (double)nc * opnd_w) * kw;
     }
 }
 
 void leaf_work(const Ctx& c, int64_t c0, double& flops, double& bytes)
 {
     flops = bytes = 0.0;
-    const double elt = c.plan.dtype == 0 ? 8.0 : 4.0;
+    const double elt = c.plan.dtype == 0 ? 8.0 : c.plan.dtype == 2 ? 16.0 : 4.0;
     const double sides = c.plan.herm ? 1.0 : 2.0;  // LU also solves the row panel
+    const int64_t lw = c.plan.leaf;
     for (int64_t n : *c.ns) {
         if (c0 >= n) continue;
-        const double bs = (double)((n - c0) < kLeaf ? (n - c0) : kLeaf);
+        const double bs = (double)((n - c0) < lw ? (n - c0) : lw);
         const double m = (double)(n - c0) - bs;
-        flops += bs * bs * bs / 3.0 * (c.plan.herm ? 1.0 : 2.0) + sides * m * bs * bs;
-        bytes += (bs * bs + 2.0 * sides * m * bs) * elt + sides * m * bs * 4.0 * c.plan.pieces;
+        flops += (bs * bs * bs / 3.0 * (c.plan.herm ? 1.0 : 2.0) + sides * m * bs * bs) *
+                 (c.plan.cplx ? 4.0 : 1.0);
+        bytes += (bs * bs + 2.0 * sides * m * bs) * elt +
+                 sides * m * bs * 4.0 * c.plan.pieces * (c.plan.cplx ? 3.0 : 1.0);
     }
 }
 
@@ -239,6 +258,11 @@ dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
 {
     double fl = 0, by = 0;
     if (c.profiling) leaf_work(c, c0, fl, by);
+    if (c.plan.cplx)
+        return timed(c, c.plan.herm ? K_LEAF_ZLDLH : K_LEAF_ZLU, fl, by, [&] {
+            return dpp::launch_leaf_complex(c.plan.herm, c.plan.pieces, c.probs, c.count, c.nmax,
+                                            c0, j0, c.plan.ss, c.s);
+        });
     if (c.plan.herm)
         return timed(c, K_LEAF_LDLH, fl, by, [&] {
             return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.pieces, c.probs, c.count, c.nmax, c0,
@@ -257,7 +281,7 @@ dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
 dpp_status factor_panel(const Ctx& c, int64_t c0, int64_t w, int64_t j0)
 {
     if (c0 >= c.pmax) return DPP_OK;
-    if (w <= kLeaf) return leaf(c, c0, j0);
+    if (w <= c.plan.leaf) return leaf(c, c0, j0);
     const int64_t h = w / 2, mid = c0 + h;
     dpp_status st = factor_panel(c, c0, h, j0);
     if (st != DPP_OK || mid >= c.nmax) return st;
@@ -276,15 +300,16 @@ dpp_status lu_panel(const Ctx& c, int64_t j0)
 {
     const int64_t j1 = j0 + c.plan.B0;
     constexpr int64_t kAll = (int64_t)1 << 62;
-    for (int64_t c0 = j0; c0 < j1 && c0 < c.pmax; c0 += kLeaf) {
+    const int lw = c.plan.leaf;
+    for (int64_t c0 = j0; c0 < j1 && c0 < c.pmax; c0 += lw) {
         dpp_status st = leaf(c, c0, j0);
         if (st != DPP_OK) return st;
-        const int64_t x = c0 + kLeaf;
+        const int64_t x = c0 + lw;
         if (x >= j1 || x >= c.nmax) continue;
-        st = update(c, dpp::Region{x, kAll, x, j1 - x}, c0, kLeaf, j0);
+        st = update(c, dpp::Region{x, kAll, x, j1 - x}, c0, lw, j0);
         if (st != DPP_OK) return st;
         if (j1 < c.nmax) {
-            st = update(c, dpp::Region{x, j1 - x, j1, kAll}, c0, kLeaf, j0);
+            st = update(c, dpp::Region{x, j1 - x, j1, kAll}, c0, lw, j0);
             if (st != DPP_OK) return st;
         }
     }
@@ -318,9 +343,9 @@ dpp_status run_group(const Ctx& c)
 // with the same leading dimension (in place) or storage disjoint from A's.
 bool source_ok(const dpp_problem& q, dpp_dtype dt)
 {
-    if (q.ldk < q.n || q.ldk > kMaxLda) return false;
+    if (q.ldk < q.n || q.ldk > max_lda(dt)) return false;
     if (q.K == q.A) return q.ldk == q.lda;
-    const uintptr_t elt = dt == DPP_F64 ? 8 : 4;
+    const uintptr_t elt = dt == DPP_F64 ? 8 : dt == DPP_C128 ? 16 : 4;
     const uintptr_t a0 = reinterpret_cast<uintptr_t>(q.A), k0 = reinterpret_cast<uintptr_t>(q.K);
     const uintptr_t a1 = a0 + (uintptr_t)((q.n - 1) * q.lda + q.n) * elt;
     const uintptr_t k1 = k0 + (uintptr_t)((q.n - 1) * q.ldk + q.n) * elt;
@@ -334,11 +359,12 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     int64_t nmax = 0;
     for (int64_t i = 0; i < count; ++i) {
         const dpp_problem& q = probs[i];
-        if (q.n < 1 || q.lda < q.n || q.lda > kMaxLda || !q.A || !q.u || !q.mask || !q.pivots ||
-            !q.loglik || !q.info)
+        if (q.n < 1 || q.lda < q.n || q.lda > max_lda(dt) || !q.A || !q.u || !q.mask ||
+            !q.pivots || !q.loglik || !q.info)
             return DPP_ERR_INVALID_ARG;
         if (q.K && !source_ok(q, dt)) return DPP_ERR_INVALID_ARG;
-        if (q.npiv < 0 || q.npiv > q.n || (q.npiv % dpp::kLeaf != 0 && q.npiv != q.n))
+        const int64_t lw = dt == DPP_C128 ? dpp::kLeafC : dpp::kLeaf;
+        if (q.npiv < 0 || q.npiv > q.n || (q.npiv % lw != 0 && q.npiv != q.n))
             return DPP_ERR_INVALID_ARG;
         nmax = q.n > nmax ? q.n : nmax;
     }
@@ -387,7 +413,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.info = q.info;
         d.stats = q.stats;
         d.diag = reinterpret_cast<double*>(base_of[(size_t)i]);
-        d.split = plan.pieces ? reinterpret_cast<uint16_t*>(base_of[(size_t)i] + diag_bytes(q.n))
+        d.split = plan.pieces ? reinterpret_cast<uint16_t*>(base_of[(size_t)i] + diag_bytes(plan, q.n))
                               : nullptr;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -431,7 +457,7 @@ size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t cou
     if (!ns || count < 1 || !valid_enums(dt, prec)) return 0;
     int64_t nmax = 0;
     for (int64_t i = 0; i < count; ++i) {
-        if (ns[i] < 1 || ns[i] > kMaxLda) return 0;
+        if (ns[i] < 1 || ns[i] > max_lda(dt)) return 0;
         nmax = ns[i] > nmax ? ns[i] : nmax;
     }
     const Plan plan = make_plan(herm, dt, prec, nmax);

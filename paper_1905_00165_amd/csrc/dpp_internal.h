@@ -10,6 +10,25 @@ namespace dpp {
 // Width of the diagonal block whose keep/reject decisions one wavefront makes
 // (one matrix row per lane of the 64-wide wavefront).
 constexpr int kLeaf = 64;
+// The same for complex kernels: 32 complex columns, whose real and imaginary
+// parts are the 64 real columns of the block's real form (see below), so a
+// lane's row still fits the same registers and the panel solves and updates
+// see 64-wide real blocks.
+constexpr int kLeafC = 32;
+
+// Complex kernels (storage: interleaved real and imaginary parts, column-major,
+// leading dimension in complex entries) run their solves and Schur updates in
+// real arithmetic on real forms of the complex factors. Complex column p of a
+// panel becomes real columns 2p (real part) and 2p + 1 (imaginary part); the
+// Schur complement C, viewed as a real matrix with rows 2i + s (s = 0: real
+// part, 1: imaginary part of complex row i) and complex columns j, lies in
+// memory as a column-major real matrix with leading dimension 2 lda. Then
+//   LDL^H: C -= L W^H, W = L D:  C'[2i + s][j] -= sum_k' L'[2i + s][k'] W'[j][k']
+//     with W'[j] = (Re W_jp, Im W_jp)_p, L'[2i] = (Re L_ip, Im L_ip)_p and
+//     L'[2i + 1] = (Im L_ip, -Re L_ip)_p;
+//   LU: C -= L U, B = U^T: W'[j] = (Re B_jp, Im B_jp)_p, L'[2i] = (Re L_ip,
+//     -Im L_ip)_p and L'[2i + 1] = (Im L_ip, Re L_ip)_p,
+// i.e. a real product with twice the rows of L and twice the inner dimension.
 
 // Per-problem descriptor as the kernels read it (device memory).
 struct DevProb {
@@ -57,7 +76,15 @@ __device__ __forceinline__ const T* first_source(const DevProb& P, bool first, i
 // of 16 values (32 bytes) back to back. So the 16 rows x 32 columns an update
 // stage copies are two contiguous 512-byte runs, and 32 rows x 16 columns one
 // 1 KiB run; 8 consecutive columns of one row (16 bytes) stay contiguous.
+// For complex kernels the planes of L hold the 2n rows of L' (one per real
+// row of C) and those of B the n rows of W', both with ss real k columns.
 __host__ __device__ inline int64_t plane_rows(int64_t n) { return (n + 31) / 32 * 32; }
+__host__ __device__ inline uint16_t* split_plane(uint16_t* base, int64_t nl, int64_t nb, int ss,
+                                                 int np, int q)
+{
+    return q < np ? base + (int64_t)q * plane_rows(nl) * ss
+                  : base + ((int64_t)np * plane_rows(nl) + (int64_t)(q - np) * plane_rows(nb)) * ss;
+}
 __host__ __device__ inline uint16_t* split_plane(uint16_t* base, int64_t n, int ss, int q)
 {
     return base + (int64_t)q * plane_rows(n) * ss;
@@ -80,6 +107,11 @@ hipError_t launch_leaf_ldlh(int dtype, int pieces, const DevProb* probs, int npr
                             int64_t c0, int64_t j0, int ss, hipStream_t s);
 hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
                           int64_t c0, int64_t j0, int ss, hipStream_t s);
+// Complex kernels (storage dtype 2): the diagonal block [c0, c0 + kLeafC) in
+// complex columns; the split planes hold the real forms L' and W' at real
+// column 2 (c0 - j0) of the outer panel.
+hipError_t launch_leaf_complex(bool herm, int pieces, const DevProb* probs, int nprob,
+                               int64_t nmax, int64_t c0, int64_t j0, int ss, hipStream_t s);
 
 // Schur-complement update of rows [base, n) x cols [base, min(base+ncols, n))
 // by the K range [k0, k0+kw) of the factored columns; herm: lower part only.
@@ -96,6 +128,8 @@ inline Region trailing_region(int64_t base, int64_t ncols)
     return Region{base, (int64_t)1 << 62, base, ncols};
 }
 
+// dtype 0: FP64 storage, 1: FP32, 2: complex (FP64 parts; region, k0 and kw
+// in complex rows and columns, the products on the real forms).
 hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
                              Region rg, int64_t k0, int kw, hipStream_t s);
 // Split-BF16 form: the products of the `pieces` (2 or 3) BF16 pieces of L and

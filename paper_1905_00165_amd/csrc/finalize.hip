@@ -87,6 +87,22 @@ __global__ __launch_bounds__(256) void store_diag(const DevProb* __restrict__ pr
     }
 }
 
+// Complex kernels: blocks of kLeafC complex columns (16 bytes per entry).
+template <bool HERM>
+__global__ __launch_bounds__(256) void store_diag_c(const DevProb* __restrict__ probs)
+{
+    const DevProb P = probs[blockIdx.y];
+    const int64_t c0 = (int64_t)blockIdx.x * kLeafC;
+    if (c0 >= P.npiv) return;
+    const int bs = (int)((P.n - c0) < kLeafC ? (P.n - c0) : kLeafC);
+    const double2* blk = reinterpret_cast<const double2*>(P.diag) + (int64_t)blockIdx.x * kLeafC * kLeafC;
+    double2* A = static_cast<double2*>(P.A);
+    for (int e = threadIdx.x; e < kLeafC * kLeafC; e += 256) {
+        const int i = e % kLeafC, k = e / kLeafC;
+        if (i < bs && k < bs && (!HERM || k <= i)) A[(c0 + i) + (c0 + k) * P.lda] = blk[e];
+    }
+}
+
 struct DescChunk {
     DevProb d[kDescPerLaunch];
     int cnt;
@@ -113,6 +129,12 @@ hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStr
 hipError_t launch_store_diag(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
                              hipStream_t s)
 {
+    if (dtype == 2) {
+        dim3 gridc((unsigned)((nmax + kLeafC - 1) / kLeafC), nprob);
+        if (herm) hipLaunchKernelGGL((store_diag_c<true>), gridc, dim3(256), 0, s, probs);
+        else hipLaunchKernelGGL((store_diag_c<false>), gridc, dim3(256), 0, s, probs);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)((nmax + kLeaf - 1) / kLeaf), nprob);
     if (herm) {
         if (dtype == 0) hipLaunchKernelGGL((store_diag<double, true>), grid, dim3(256), 0, s, probs);

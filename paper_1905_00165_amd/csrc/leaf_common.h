@@ -148,11 +148,11 @@ __device__ __forceinline__ void split_pieces(double x, uint32_t (&p)[NPC])
 }
 
 // Writes the NPC pieces of 8 consecutive panel values v[0..7] of row r,
-// columns kk .. kk+7 of the outer panel (kk a multiple of 8), to the planes
-// q0 .. q0 + NPC - 1: one 16-byte store per plane.
+// columns kk .. kk+7 of the outer panel (kk a multiple of 8): piece i goes to
+// the plane at first + i * stride (elements), one 16-byte store per plane.
 template <int NPC>
-__device__ __forceinline__ void store_pieces8(uint16_t* base, int64_t n, int ss, int q0, int64_t r,
-                                              int kk, const double (&v)[8])
+__device__ __forceinline__ void store_pieces8_at(uint16_t* first, int64_t stride, int ss, int64_t r,
+                                                 int kk, const double (&v)[8])
 {
     if constexpr (NPC > 0) {
         uint32_t w[NPC][4];
@@ -167,9 +167,16 @@ __device__ __forceinline__ void store_pieces8(uint16_t* base, int64_t n, int ss,
         const int64_t o = plane_off(r, kk, ss);
 #pragma unroll
         for (int i = 0; i < NPC; ++i)
-            *reinterpret_cast<uint4*>(split_plane(base, n, ss, q0 + i) + o) =
+            *reinterpret_cast<uint4*>(first + i * stride + o) =
                 make_uint4(w[i][0], w[i][1], w[i][2], w[i][3]);
     }
+}
+// Real kernels: the planes q0 .. q0 + NPC - 1 of a problem of size n.
+template <int NPC>
+__device__ __forceinline__ void store_pieces8(uint16_t* base, int64_t n, int ss, int q0, int64_t r,
+                                              int kk, const double (&v)[8])
+{
+    store_pieces8_at<NPC>(split_plane(base, n, ss, q0), plane_rows(n) * ss, ss, r, kk, v);
 }
 
 // ------------------------------------------------------------ panel solves

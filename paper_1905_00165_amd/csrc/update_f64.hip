@@ -18,6 +18,13 @@
 // current one is multiplied. For LDL^H only tiles on or below the diagonal are launched.
 // Workgroup b runs tile (b % 8) * (G / 8) + b / 8 (G, the grid size, is a
 // multiple of 8), so each XCD takes a contiguous range of tiles.
+//
+// Complex kernels (CPLX) run the same product on the real forms of the
+// factors (dpp_internal.h): a tile is 128 real rows of C' (64 complex rows)
+// by 128 complex columns, and each staged chunk of 16 real k (8 complex
+// columns) is built from the complex panel in A as it is stored to LDS: L'
+// rows 2i and 2i + 1 from L_i, W' from W = L D' (LDL^H) or from the rows of U
+// (LU). Hermitian tiles entirely above the diagonal exit at once.
 #include "dpp_internal.h"
 
 namespace dpp {
@@ -74,10 +81,12 @@ __device__ __forceinline__ void gstore(T* p, double v)
     *(__attribute__((address_space(1))) T*)(p) = (T)v;
 }
 
-template <typename T, bool HERM>
+template <typename T, bool HERM, bool CPLX>
 __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__ probs, Region rg,
                                                   int64_t k0, int kw)
 {
+    static_assert(!CPLX || sizeof(T) == 8, "complex storage: FP64 parts");
+    constexpr int RS = CPLX ? 2 : 1;  // real rows of C per row of the region
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
     const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
@@ -86,17 +95,21 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     if (nrows <= 0 || ncols <= 0 || k0 + kw > n || k0 >= P.npiv) return;
     // Only decided columns contribute: k in [k0, min(k0 + kw, npiv)).
     if (k0 + kw > P.npiv) kw = (int)(P.npiv - k0);
-    const int64_t NR = (nrows + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
+    const int64_t NR = (nrows * RS + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
     // XCD-contiguous tile order (grid size is a multiple of 8).
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     TileCoord tc;
-    if (!tile_of(t, NR, NC, HERM, tc)) return;
+    if (!tile_of(t, NR, NC, HERM && !CPLX, tc)) return;
+    // Complex Hermitian: skip tiles entirely above the diagonal.
+    if (CPLX && HERM && rg.r0 + (tc.i0 + TM - 1) / RS < rg.c0 + tc.j0) return;
 
+    // C as a real column-major matrix: RS real rows per row of the region.
     T* __restrict__ A = static_cast<T*>(P.A);
-    const int64_t lda = P.lda;
+    const int64_t lda = P.lda * RS;
     int64_t lds_;  // leading dimension of the source C is read from (K when k0 == 0)
     const T* __restrict__ Csrc = first_source<T>(P, k0 == 0, lds_);
+    lds_ *= RS;
     const double* __restrict__ piv = P.piv;
 
     // Two LDS buffers: chunk c + 1 is loaded into registers while chunk c is
@@ -115,8 +128,9 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int64_t rowA0 = rg.r0 + tc.i0;  // global row of tile row 0
-    const int64_t colB0 = rg.c0 + tc.j0;  // global col of tile col 0
+    const int64_t rowA0 = rg.r0 * RS + tc.i0;  // real row of C at tile row 0
+    const int64_t colB0 = rg.c0 + tc.j0;       // column of C at tile col 0
+    const int64_t rEndR = rEnd * RS;
 
     // Register staging of one chunk. A: thread -> (i = tid % 128, kk = tid/128 + 2q).
     // B (LDL^H): (j = tid % 128, kk = tid/128 + 2q), B[k][c] = L[c][k] * d'_k.
@@ -126,8 +140,45 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     // nothing uses their values before store_chunk, so they stay in flight
     // during the current chunk's products; the pivot scaling of B happens at
     // the store for the same reason.
+    // Complex: A: (complex row i = tid % 64, complex k = tid/64 + 4q, q < 2);
+    // B (LDL^H): (j = tid % 128, complex k = tid/128 + 2q, q < 4); B (LU):
+    // (complex k = tid % 8, j = tid/8 + 32q, q < 4); each complex value fills
+    // its entries of the real forms at the store.
     double ra[KC / 2], rb[KC / 2], rp[KC / 2];
     auto load_chunk = [&](int kc) {
+        if constexpr (CPLX) {
+            const int64_t kb = k0 + kc / 2;  // first complex column of the chunk
+            const int64_t r0c = rowA0 / 2;
+            const int64_t gr = r0c + (tid & 63) < rEnd ? r0c + (tid & 63) : rEnd - 1;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const T* p = A + 2 * (gr + (kb + (tid >> 6) + 4 * q) * P.lda);
+                ra[2 * q] = gload(p);
+                ra[2 * q + 1] = gload(p + 1);
+            }
+            if constexpr (HERM) {
+                const int64_t gc = colB0 + (tid & (TN - 1)) < cEnd ? colB0 + (tid & (TN - 1)) : cEnd - 1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t gk = kb + (tid >> 7) + 2 * q;
+                    const T* p = A + 2 * (gc + gk * P.lda);
+                    rb[2 * q] = gload(p);
+                    rb[2 * q + 1] = gload(p + 1);
+                    rp[q] = gload(piv + gk);
+                }
+            } else {
+                const int64_t gk = kb + (tid & 7);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t gc0 = colB0 + (tid >> 3) + 32 * q;
+                    const int64_t gc = gc0 < cEnd ? gc0 : cEnd - 1;
+                    const T* p = A + 2 * (gk + gc * P.lda);
+                    rb[2 * q] = gload(p);
+                    rb[2 * q + 1] = gload(p + 1);
+                }
+            }
+            return;
+        }
         {
             const int64_t gr = rowA0 + (tid & (TM - 1)) < rEnd ? rowA0 + (tid & (TM - 1)) : rEnd - 1;
 #pragma unroll
@@ -155,6 +206,35 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
         }
     };
     auto store_chunk = [&](int buf) {
+        if constexpr (CPLX) {
+            // L' rows 2i, 2i + 1 (HERM: (Re, Im), (Im, -Re); LU: (Re, -Im), (Im, Re)).
+            const int i = tid & 63;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int kk = 2 * ((tid >> 6) + 4 * q);
+                const double re = ra[2 * q], im = ra[2 * q + 1];
+                sA[buf][kk][2 * i] = re;
+                sA[buf][kk + 1][2 * i] = HERM ? im : -im;
+                sA[buf][kk][2 * i + 1] = im;
+                sA[buf][kk + 1][2 * i + 1] = HERM ? -re : re;
+            }
+            if constexpr (HERM) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = 2 * ((tid >> 7) + 2 * q);
+                    sB[buf][kk][tid & (TN - 1)] = rb[2 * q] * rp[q];
+                    sB[buf][kk + 1][tid & (TN - 1)] = rb[2 * q + 1] * rp[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = 2 * (tid & 7);
+                    sB[buf][kk][(tid >> 3) + 32 * q] = rb[2 * q];
+                    sB[buf][kk + 1][(tid >> 3) + 32 * q] = rb[2 * q + 1];
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < KC / 2; ++q) sA[buf][(tid >> 7) + 2 * q][tid & (TM - 1)] = ra[q];
         if constexpr (HERM) {
@@ -170,7 +250,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     load_chunk(0);
     store_chunk(0);
     __syncthreads();
-    const int nchunks = kw / KC;
+    const int nchunks = kw * RS / KC;
     for (int ch = 0; ch < nchunks; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nchunks) load_chunk((ch + 1) * KC);
@@ -205,14 +285,14 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
         const int64_t gr = rowA0 + wm * 64 + bi * 16 + (lane & 15);
         T* const rowp = A + gr;
         const T* const srcp = Csrc + gr;
-        // All loads of this 16-row block before any store (see update_bf16x3.hip).
+        // All loads of this 16-row block before any store (see update_split.hip).
         double cv[4][4];
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
-                const bool ok = gr < rEnd && gc < cEnd && (!HERM || gr >= gc);
+                const bool ok = gr < rEndR && gc < cEnd && (!HERM || gr / RS >= gc);
                 cv[bj][e] = ok ? gload(srcp + gc * lds_) : 0.0;
             }
 #pragma unroll
@@ -220,7 +300,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
-                const bool ok = gr < rEnd && gc < cEnd && (!HERM || gr >= gc);
+                const bool ok = gr < rEndR && gc < cEnd && (!HERM || gr / RS >= gc);
                 if (ok) gstore(rowp + gc * lda, cv[bj][e] - acc[bi][bj][e]);
             }
     }
@@ -235,15 +315,20 @@ hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int npr
     const int64_t nc = (rg.c0 + rg.clen < nmax ? rg.c0 + rg.clen : nmax) - rg.c0;
     if (nrows <= 0 || nc <= 0) return hipSuccess;
     if (herm && rg.r0 != rg.c0) return hipErrorInvalidValue;
-    const int64_t NR = (nrows + TM - 1) / TM, NC = (nc + TN - 1) / TN;
-    const int64_t tiles = herm ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
+    const bool cplx = dtype == 2;
+    if (kw % (cplx ? KC / 2 : KC) != 0) return hipErrorInvalidValue;
+    const int64_t NR = (nrows * (cplx ? 2 : 1) + TM - 1) / TM, NC = (nc + TN - 1) / TN;
+    const int64_t tiles = herm && !cplx ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
     dim3 grid((unsigned)((tiles + 7) / 8 * 8), nprob), block(256);
-    if (herm) {
-        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true>), grid, block, 0, s, probs, rg, k0, kw);
-        else hipLaunchKernelGGL((update_f64<float, true>), grid, block, 0, s, probs, rg, k0, kw);
+    if (cplx) {
+        if (herm) hipLaunchKernelGGL((update_f64<double, true, true>), grid, block, 0, s, probs, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<double, false, true>), grid, block, 0, s, probs, rg, k0, kw);
+    } else if (herm) {
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true, false>), grid, block, 0, s, probs, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, true, false>), grid, block, 0, s, probs, rg, k0, kw);
     } else {
-        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false>), grid, block, 0, s, probs, rg, k0, kw);
-        else hipLaunchKernelGGL((update_f64<float, false>), grid, block, 0, s, probs, rg, k0, kw);
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false, false>), grid, block, 0, s, probs, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, false, false>), grid, block, 0, s, probs, rg, k0, kw);
     }
     return hipGetLastError();
 }

@@ -224,46 +224,56 @@ __device__ __forceinline__ bool grouped_tile(int64_t t, int64_t NR, int64_t NC, 
     return false;
 }
 
-template <typename T, bool HERM, class S>
+// CPLX: complex kernels (T = double, the parts of complex entries). Region,
+// k0, kw and j0 count complex rows and columns; the tile runs over the real
+// rows of C' (two per complex row) and the real k of the planes (two per
+// complex column), dpp_internal.h.
+template <typename T, bool HERM, class S, bool CPLX>
 __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, Region rg, int64_t k0,
                                             int kw, int64_t j0, int ss, unsigned char* lds)
 {
+    constexpr int RS = CPLX ? 2 : 1;  // real rows (and real k) per complex one
     const DevProb P = probs[blockIdx.y];
     const int64_t n = P.n;
-    const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
+    const int64_t rEndC = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
     const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
-    const int64_t nrows = rEnd - rg.r0, ncols = cEnd - rg.c0;
+    const int64_t nrows = rEndC - rg.r0, ncols = cEnd - rg.c0;
     if (nrows <= 0 || ncols <= 0 || k0 + kw > n || k0 >= P.npiv) return;
     // Only decided columns contribute: k in [k0, min(k0 + kw, npiv)).
-    const int kwp = k0 + kw <= P.npiv ? kw : (int)(P.npiv - k0);
-    const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (ncols + S::TN - 1) / S::TN;
+    const int kwp = RS * (k0 + kw <= P.npiv ? kw : (int)(P.npiv - k0));
+    const int64_t NR = (nrows * RS + S::TM - 1) / S::TM, NC = (ncols + S::TN - 1) / S::TN;
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     TileCoord tc;
     if constexpr (S::TM == S::TN) {
-        if (!grouped_tile(t, NR, NC, HERM, tc)) return;
+        if (!grouped_tile(t, NR, NC, HERM && !CPLX, tc)) return;
     } else {
         if (t >= NR * NC) return;
         tc.i0 = t % NR;
         tc.j0 = t / NR;
-        // Hermitian: skip tiles entirely above the diagonal.
-        if (HERM && (tc.i0 + 1) * S::TM <= tc.j0 * S::TN) return;
+        if (HERM && !CPLX && (tc.i0 + 1) * S::TM <= tc.j0 * S::TN) return;
     }
+    // Hermitian: skip tiles entirely above the diagonal (complex: by the
+    // complex row of the tile's last real row).
+    if (CPLX && HERM && (tc.i0 * S::TM + S::TM - 1) / RS < tc.j0 * S::TN) return;
 
+    // C as a real column-major matrix with RS real rows per row of the region.
     T* __restrict__ A = static_cast<T*>(P.A);
-    const int64_t lda = P.lda;
+    const int64_t lda = P.lda * RS;
     int64_t lds_;  // leading dimension of the source C is read from (K when k0 == 0)
     const T* __restrict__ Csrc = first_source<T>(P, k0 == 0, lds_);
+    lds_ *= RS;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave / S::WC, wc = wave % S::WC;
 
-    const int64_t rowT0 = rg.r0 + tc.i0 * S::TM;
+    const int64_t rowT0 = rg.r0 * RS + tc.i0 * S::TM;  // real rows of C'
     const int64_t colT0 = rg.c0 + tc.j0 * S::TN;
     const int64_t colEnd = cEnd;
-    const int kk0 = (int)(k0 - j0);
+    const int64_t rEnd = rEndC * RS;
+    const int kk0 = (int)(RS * (k0 - j0));
 
     // Direct-to-LDS copies. Copy i of a stage writes bytes [1024 i, 1024 i + 1024)
     // of the buffer (the pieces of L, then of W, back to back): 1024 / ROWB rows of
@@ -291,7 +301,8 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
             int64_t g = first + row0 + rl;
             g = g < last ? g : last;
             __builtin_amdgcn_global_load_lds(
-                (gptr_t)(split_plane(P.split, n, ss, plane) + plane_off(g, kk0 + kc + seg8, ss)),
+                (gptr_t)(split_plane(P.split, RS * n, n, ss, S::NP, plane) +
+                         plane_off(g, kk0 + kc + seg8, ss)),
                 (lptr_t)(lds + buf * S::BUF + off), 16, 0, 0);
         }
     };
@@ -309,7 +320,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
     // Rounds r = (rb, pair of column blocks); each round is 32 values per lane.
     const int rlim = (int)(rEnd - rowT0);
     const int clim = (int)(colEnd - colT0);
-    const int dd = (int)(colT0 - rowT0);
+    const int dd = (int)(colT0 - rowT0 / RS);
     const int jl = wc * (S::TN / S::WC) + 4 * (lane >> 5);  // lane part of the column
     constexpr int CP = S::EP;                                // column blocks per round
     constexpr int ROUNDS = S::RB * (S::CB / CP);
@@ -324,13 +335,16 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
     auto c_ok = [&](int rb, int ju) {
         const int i = wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
         const int j = jl + ju;
-        return i < rlim && j < clim && (!HERM || i - j >= dd);
+        // Complex: the real row i of the tile is complex row (rowT0 + i) / 2
+        // (rowT0 is even), i.e. i / 2 - j >= dd with dd = colT0 - rowT0 / 2.
+        return i < rlim && j < clim && (!HERM || (CPLX ? (i >> 1) : i) - j >= dd);
     };
     // Interior tiles (fully inside the region and, for the lower part, fully
     // below the diagonal) take a branch-free path: raw buffer loads and stores
     // with one per-lane offset and a scalar per-column offset. Edge tiles use
     // per-element predicates.
-    const bool interior = rlim >= S::TM && clim >= S::TN && (!HERM || -dd >= S::TN - 1);
+    const bool interior = rlim >= S::TM && clim >= S::TN &&
+                          (!HERM || (CPLX ? rowT0 / RS >= colT0 + S::TN - 1 : -dd >= S::TN - 1));
     const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
         A + rowT0 + colT0 * lda, 0,
         (int)(((int64_t)S::TN * lda) * (int64_t)sizeof(T) < 0x7fffffff
@@ -498,40 +512,40 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
 }
 
 // The two product forms as separate kernels, so that profiles tell them apart.
-template <typename T, bool HERM, class S>
+template <typename T, bool HERM, class S, bool CPLX>
 __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevProb* __restrict__ probs,
                                                                      Region rg, int64_t k0, int kw,
                                                                      int64_t j0, int ss)
 {
     static_assert(S::NP == 2, "three products from two pieces");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    update_body<T, HERM, S>(probs, rg, k0, kw, j0, ss, lds);
+    update_body<T, HERM, S, CPLX>(probs, rg, k0, kw, j0, ss, lds);
 }
-template <typename T, bool HERM, class S>
+template <typename T, bool HERM, class S, bool CPLX>
 __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x6(const DevProb* __restrict__ probs,
                                                                      Region rg, int64_t k0, int kw,
                                                                      int64_t j0, int ss)
 {
     static_assert(S::NP == 3, "six products from three pieces");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    update_body<T, HERM, S>(probs, rg, k0, kw, j0, ss, lds);
+    update_body<T, HERM, S, CPLX>(probs, rg, k0, kw, j0, ss, lds);
 }
 
-template <typename T, bool HERM, class S>
+template <typename T, bool HERM, class S, bool CPLX>
 constexpr auto kernel_of()
 {
-    if constexpr (S::NP == 2) return update_bf16x3<T, HERM, S>;
-    else return update_bf16x6<T, HERM, S>;
+    if constexpr (S::NP == 2) return update_bf16x3<T, HERM, S, CPLX>;
+    else return update_bf16x6<T, HERM, S, CPLX>;
 }
 
-template <typename T, bool HERM, class S>
+template <typename T, bool HERM, class S, bool CPLX>
 hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, Region rg,
                         int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
-    const int64_t NR = (nrows + S::TM - 1) / S::TM, NC = (nc + S::TN - 1) / S::TN;
-    const int64_t tiles = (HERM && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
+    const int64_t NR = (nrows * (CPLX ? 2 : 1) + S::TM - 1) / S::TM, NC = (nc + S::TN - 1) / S::TN;
+    const int64_t tiles = (HERM && !CPLX && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
     const unsigned grid_x = (unsigned)((tiles + 7) / 8 * 8);  // XCD remap needs a multiple of 8
-    const auto k = kernel_of<T, HERM, S>();
+    const auto k = kernel_of<T, HERM, S, CPLX>();
     // The dynamic-LDS limit is a per-device function attribute: set it once
     // on each device the kernel runs on.
     static std::atomic<uint64_t> attr_set{0};
@@ -549,7 +563,7 @@ hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t 
     return hipGetLastError();
 }
 
-template <typename T, bool HERM, int NP>
+template <typename T, bool HERM, int NP, bool CPLX>
 hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, Region rg,
                     int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
@@ -558,22 +572,26 @@ hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, 
     using Wide = std::conditional_t<NP == 2, Wide3, Wide6>;
     // The tile shape follows the width of the updated column range.
     if (nc <= 128)
-        return launch_shape<T, HERM, Narrow>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        return launch_shape<T, HERM, Narrow, CPLX>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
     if (nc <= 256)
-        return launch_shape<T, HERM, Medium>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    return launch_shape<T, HERM, Wide>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        return launch_shape<T, HERM, Medium, CPLX>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    return launch_shape<T, HERM, Wide, CPLX>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
 }
 
 template <int NP>
 hipError_t launch_np(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nrows,
                      int64_t nc, Region rg, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
-    if (herm) {
-        if (dtype == 0) return launch_t<double, true, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-        return launch_t<float, true, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    if (dtype == 2) {
+        if (herm) return launch_t<double, true, NP, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        return launch_t<double, false, NP, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
     }
-    if (dtype == 0) return launch_t<double, false, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    return launch_t<float, false, NP>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    if (herm) {
+        if (dtype == 0) return launch_t<double, true, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        return launch_t<float, true, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    }
+    if (dtype == 0) return launch_t<double, false, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    return launch_t<float, false, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
 }
 
 }  // namespace
@@ -585,7 +603,9 @@ hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* 
     const int64_t nrows = (rg.r0 + rg.rlen < nmax ? rg.r0 + rg.rlen : nmax) - rg.r0;
     const int64_t nc = (rg.c0 + rg.clen < nmax ? rg.c0 + rg.clen : nmax) - rg.c0;
     if (nrows <= 0 || nc <= 0) return hipSuccess;
-    if (kw % kKAlign != 0 || (herm && rg.r0 != rg.c0)) return hipErrorInvalidValue;
+    // Every stage covers kKAlign real k: 32 real or 16 complex columns.
+    if ((kw * (dtype == 2 ? 2 : 1)) % kKAlign != 0 || (herm && rg.r0 != rg.c0))
+        return hipErrorInvalidValue;
     if (pieces == 2) return launch_np<2>(herm, dtype, probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
     if (pieces == 3) return launch_np<3>(herm, dtype, probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
     return hipErrorInvalidValue;

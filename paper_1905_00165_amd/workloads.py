@@ -205,30 +205,54 @@ def hermitize_lower(K: np.ndarray) -> np.ndarray:
     return np.tril(K, -1) + np.tril(K, -1).conj().T + np.diag(np.real(np.diag(K)))
 
 
-def complex_hermitian_kernel(n: int, seed: int, beta: bool = False) -> np.ndarray:
+def complex_hermitian_kernel(n: int, seed: int, beta: bool = False, device=None):
     """K = Q diag(lam) Q^H, Q unitary from QR of a complex Gaussian matrix,
-    lam_i ~ U(0, 1) (or Beta(0.5, 2) with `beta`); complex128, column-major."""
+    lam_i ~ U(0, 1) (or Beta(0.5, 2) with `beta`); complex128, column-major.
+
+    With ``device`` (a torch CUDA device) the QR and the products run there
+    from the same host draws and a column-major device tensor is returned
+    (the same construction; the bytes differ from the host path's)."""
     rng = np.random.default_rng(seed)
-    Q = _complex_orthonormal(rng, n)
+    if device is None:
+        Q = _complex_orthonormal(rng, n)
+        lam = rng.beta(0.5, 2.0, size=n) if beta else rng.random(n)
+        return np.asfortranarray(hermitize_lower((Q * lam) @ Q.conj().T))
+    import torch
+    G = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
     lam = rng.beta(0.5, 2.0, size=n) if beta else rng.random(n)
-    return np.asfortranarray(hermitize_lower((Q * lam) @ Q.conj().T))
+    Q, _ = torch.linalg.qr(torch.from_numpy(G).to(device))
+    del G
+    K = (Q * torch.from_numpy(lam).to(device)) @ Q.conj().T
+    del Q
+    low = torch.tril(K, -1)
+    K = low + low.conj().T + torch.diag(torch.diagonal(K).real.to(K.dtype))
+    return K.T.contiguous().T
 
 
-def complex_similarity_kernel(n: int, seed: int, unit_modulus: bool = False):
+def complex_similarity_kernel(n: int, seed: int, unit_modulus: bool = False, device=None):
     """A non-Hermitian complex kernel of the same DPP as a complex Hermitian
     one (Prop. 2): H as in complex_hermitian_kernel with lam ~ Beta(0.5, 2),
     S = diag(exp(z_j + i theta_j)), z ~ N(0, 0.5) (standard deviation 0.5),
     theta ~ U(0, 2 pi), K = S H S^{-1}. With `unit_modulus`, z = 0 and K is
-    Hermitian again. Returns (K, H), complex128, column-major."""
-    H = complex_hermitian_kernel(n, seed, beta=True)
+    Hermitian again. Returns (K, H), complex128, column-major (device tensors
+    with ``device``, as for complex_hermitian_kernel)."""
+    H = complex_hermitian_kernel(n, seed, beta=True, device=device)
     rng = np.random.default_rng(seed + 7_000_000)
     z = np.zeros(n) if unit_modulus else rng.normal(0.0, 0.5, size=n)
     theta = rng.uniform(0.0, 2.0 * np.pi, size=n)
     s = np.exp(z + 1j * theta)
-    K = (s[:, None] * H) / s[None, :]
+    if device is None:
+        K = (s[:, None] * H) / s[None, :]
+        if unit_modulus:
+            K = hermitize_lower(K)
+        return np.asfortranarray(K), H
+    import torch
+    st = torch.from_numpy(s).to(device)
+    K = (st[:, None] * H) / st[None, :]
     if unit_modulus:
-        K = hermitize_lower(K)
-    return np.asfortranarray(K), H
+        low = torch.tril(K, -1)
+        K = low + low.conj().T + torch.diag(torch.diagonal(K).real.to(K.dtype))
+    return K.T.contiguous().T, H
 
 
 def aztec_diamond_kernel(d: int):

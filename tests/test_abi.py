@@ -226,3 +226,25 @@ def test_noalloc_argument_errors_return_before_any_launch():
     big = (B.dpp_problem * 1)(B.dpp_problem(p, 3072, 3072, p, p, p, p, p, None, 0, 0, None))
     assert B.dpp_workspace_size(True, B.DPP_F64, 3072, 2) > B.DPP_NOALLOC_SCRATCH_BYTES
     assert f(big, 1, 0, 2, None) == 2                  # DPP_ERR_WORKSPACE
+
+
+def test_complex_workspace_and_arguments():
+    """Complex storage (DPP_C128): diagonal blocks of 32 x 32 complex entries
+    (16 KiB each), split planes holding two real rows of L' per complex row;
+    leading dimensions up to 2^19; partial problems in multiples of 32."""
+    n = 1000
+    f = B.dpp_workspace_size(True, B.DPP_C128, n, B.DPP_PREC_FP64)
+    # one 256-byte descriptor slot, then the strip of diagonal blocks
+    assert f == 256 + ((n + 31) // 32) * 32 * 32 * 16
+    s3 = B.dpp_workspace_size(True, B.DPP_C128, n, B.DPP_PREC_SPLIT_BF16)
+    ss = 2 * 1024   # real k columns of a 1024-wide complex panel (the whole n rounded to 32)
+    # two pieces of L' (2n rows, padded to 32) and of W' (n rows, padded)
+    assert s3 - f == 2 * (2016 + 1024) * ss * 2
+    assert B.dpp_workspace_size(True, B.DPP_C128, (1 << 19) + 1, B.DPP_PREC_FP64) == 0
+    f = B.lib().dpp_sample_ldlh_batched
+    p = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x2000)
+    bad_lda = (B.dpp_problem * 1)(B.dpp_problem(p, 10, (1 << 19) + 1, p, p, p, p, p, None, 0, 0, None))
+    assert f(bad_lda, 1, B.DPP_C128, 0, ws, 1 << 40, None) == 1
+    bad_npiv = (B.dpp_problem * 1)(B.dpp_problem(p, 100, 100, p, p, p, p, p, None, 0, 48, None))
+    assert f(bad_npiv, 1, B.DPP_C128, 0, ws, 1 << 40, None) == 1
