@@ -398,6 +398,83 @@ def bench_lu(torch, B, W, dev, cpu_seconds):
     return out
 
 
+def bench_complex_lu(torch, B, W, dev, cpu_seconds):
+    """Complex non-Hermitian K = S H S^-1 (DPP_C128 storage), n = 8192: H =
+    Q diag(lam) Q^H with Q unitary from the QR of a complex Gaussian matrix,
+    lam ~ Beta(0.5, 2), S = diag(exp(z + i theta)), z ~ N(0, 0.5); the
+    paper's dense complex LU experiment at a larger n. 16 samples (two
+    batched calls of 8, each with its own stream), all three precisions,
+    timed as one graph replay. TFLOP/s counts 8n^3/3 per sample (four real
+    products per complex one). With `cpu_seconds`, the complex oracle on a
+    prefix of one sample's pivots, scaled."""
+    n, per_call, calls = 8192, 8, 2
+    K, H = W.complex_similarity_kernel(n, seed=37, device=dev)
+    del H
+    torch.cuda.empty_cache()
+    streams = [torch.from_numpy(W.uniform_stream(n, seed=37000 + i)).to(dev)
+               for i in range(per_call * calls)]
+    As = [torch.empty_like(K) for _ in range(per_call)]
+    out = {"workload": "complex K = S H S^-1, H = Q diag(lam) Q^H (Q from QR of a complex Gaussian "
+                       "matrix), lam ~ Beta(0.5,2), S = diag(exp(z + i theta)), z ~ N(0, 0.5), "
+                       "theta ~ U(0, 2 pi); n = 8192, complex FP64 storage, LU; 16 samples as 2 "
+                       "batched calls of 8", "n": n, "samples": per_call * calls,
+           "flops_per_sample": 8.0 * n ** 3 / 3.0}
+    for name, prec in (("split6", B.DPP_PREC_SPLIT_BF16X6), ("split", B.DPP_PREC_SPLIT_BF16),
+                       ("fp64", B.DPP_PREC_FP64)):
+        ws = torch.empty(B.dpp_workspace_size_batched(False, B.DPP_C128, [n] * per_call, prec),
+                         dtype=torch.uint8, device=dev)
+        outs = [{"mask": torch.empty(n, dtype=torch.uint8, device=dev),
+                 "pivots": torch.empty(n, dtype=torch.float64, device=dev),
+                 "loglik": torch.empty(1, dtype=torch.float64, device=dev),
+                 "info": torch.empty(1, dtype=torch.int32, device=dev)}
+                for _ in range(per_call * calls)]
+
+        def step():
+            for c in range(calls):
+                B.dpp_sample_lu_batched(As, streams[c * per_call:(c + 1) * per_call], prec=prec,
+                                        ws=ws, outs=outs[c * per_call:(c + 1) * per_call],
+                                        Ks=[K] * per_call)
+
+        ms = graph_time(torch, step, reps=2)
+        B.dpp_profile_begin()
+        B.dpp_sample_lu_batched(As, streams[:per_call], prec=prec, ws=ws, outs=outs[:per_call],
+                                Ks=[K] * per_call)
+        prof = B.dpp_profile_end()
+        del ws
+        samples = per_call * calls
+        out[name] = {"ms_per_step": round(ms, 3), "samples_per_s": round(samples / (ms * 1e-3), 3),
+                     "tflops": round(samples * 8.0 * n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3),
+                     "info_all_zero": all(int(o["info"].item()) == 0 for o in outs),
+                     "size_mean": round(float(np.mean([int(o["mask"].sum().item()) for o in outs])), 1),
+                     "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
+                                 for k, v in prof.items()}}
+        dom = {"split6": "update_bf16x6", "split": "update_bf16x3", "fp64": "update_f64"}[name]
+        out[name]["roofline"] = roofline_entry(prof, dom, PEAK_FP64 if name == "fp64" else PEAK_BF16)
+    if cpu_seconds > 0:
+        import oracle
+        Kh = np.asfortranarray(K.cpu().numpy())
+        u0 = streams[0].cpu().numpy()
+        del As, K
+        torch.cuda.empty_cache()
+        A = np.array(Kh, order="F", copy=True)
+        t0 = time.perf_counter()
+        oracle.zlu(A, u0, npiv=2, inplace=True)
+        t_probe = time.perf_counter() - t0
+        p = int(max(2, min(n, cpu_seconds / max(t_probe / 2, 1e-6))))
+        A = np.array(Kh, order="F", copy=True)
+        t0 = time.perf_counter()
+        oracle.zlu(A, u0, npiv=p, inplace=True)
+        t = time.perf_counter() - t0
+        j = np.arange(n, dtype=np.float64)
+        frac = float(np.sum((n - j[:p]) ** 2) / np.sum((n - j) ** 2))
+        out["cpu_baseline"] = {"value": frac / t, "unit": "samples/s", "cores": oracle.omp_threads(),
+                               "kind": "oracle",
+                               "sample": f"first {p} of {n} pivots of one sample (unblocked complex "
+                                         f"FP64 LU, {frac * 100:.3f}% of the work) in {t:.1f} s, "
+                                         f"scaled"}
+    return out
+
+
 def bench_lensemble(torch, B, W, dev, count=4096):
     """`count` L-ensemble marginal kernels, n_i ~ U{64..1024}, rank 64, formed in
     FP64 and stored FP32, one sample each in one batched LDL^H call, both paths,
@@ -695,6 +772,9 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] LU n=8192")
         out["lu_n8192"] = bench_lu(torch, B, W, dev, min(args.cpu_seconds, 10.0))
+        torch.cuda.empty_cache()
+        log("[bench] complex LU n=8192")
+        out["complex_lu_n8192"] = bench_complex_lu(torch, B, W, dev, min(args.cpu_seconds, 10.0))
         torch.cuda.empty_cache()
         log("[bench] batched L-ensembles")
         out["lensemble_batch"] = bench_lensemble(torch, B, W, dev)

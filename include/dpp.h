@@ -75,9 +75,10 @@ typedef enum { DPP_F64 = 0, DPP_F32 = 1, DPP_C128 = 2 } dpp_dtype;
    with FP32 accumulation (about 2^-16 of each product is lost).
    DPP_PREC_SPLIT_BF16X6: three pieces p0 = bf16(x), p1 = bf16(x - p0),
    p2 = bf16(x - p0 - p1) and the six products p0*p0' + p0*p1' + p1*p0' +
-   p0*p2' + p2*p0' + p1*p1' on BF16 MFMA with FP32 accumulation (about 2^-24
-   of each product is lost, the FP32 accumulation's own order), at twice the
-   matrix-core work of DPP_PREC_SPLIT_BF16.
+   p0*p2' + p2*p0' + p1*p1' on BF16 MFMA (about 2^-24 of each product is
+   lost), at twice the matrix-core work of DPP_PREC_SPLIT_BF16; the FP32
+   accumulation runs over at most 64 values of k, whose sums are accumulated
+   in FP64, so the rounding of long FP32 sums does not enter.
    Every form subtracts the sum from the stored value in the storage
    precision. The diagonal-block decisions, the panel solves and the
    log-likelihood stay in FP64 on every path. */

@@ -8,9 +8,13 @@
 //   NP = 2 (update_bf16x3): hi*hi' + hi*lo' + lo*hi'; the dropped lo*lo' and
 //     the pieces' rounding leave about 2^-16 of each product;
 //   NP = 3 (update_bf16x6): p0*p0' + p0*p1' + p1*p0' + p0*p2' + p2*p0' +
-//     p1*p1'; about 2^-24 of each product is left, the order of the FP32
-//     accumulation itself.
-// The FP32 sum is subtracted from the stored value in FP64 and rounded to the
+//     p1*p1'; about 2^-24 of each product is left. FP32 sums over long k
+//     ranges would then dominate the error (each addition rounds to 2^-24 of
+//     a partial sum that can be much larger than the result), so the FP32
+//     accumulators are added into FP64 ones every 64 k (Shape::FL) and
+//     restart from zero: 64 x 64 per wavefront, one wavefront per SIMD, so
+//     that both sets fit the registers.
+// The sum is subtracted from the stored value in FP64 and rounded to the
 // storage type.
 //
 // Operands come from the split copies the diagonal-block kernel writes while it
@@ -57,14 +61,18 @@ constexpr int kGroupCols = 4;      // tile columns per group of the wide order
 
 // TM x TN tile on WR x WC wavefronts; K advances KC at a time through NST LDS
 // stages (NST - 1 of them in flight while one is multiplied); NP BF16 pieces
-// per operand value.
-template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_, int KC_, int NST_, int NP_>
+// per operand value. FL > 0: the FP32 accumulators are added into FP64 ones
+// (and restart from zero) every FL stages, so no FP32 sum runs over more than
+// FL * KC values of k.
+template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_, int KC_, int NST_, int NP_,
+          int FL_ = 0>
 struct Shape {
     static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_;
     static constexpr int MINB = MINB_;  // workgroups per CU the register budget allows
     static constexpr int EP = EP_;      // 32x32 blocks per epilogue round
     static constexpr int KC = KC_, NST = NST_;
     static constexpr int NP = NP_;                                 // pieces per value
+    static constexpr int FL = FL_;                                 // stages per FP64 flush (0: none)
     static constexpr int NTERM = NP == 2 ? 3 : 6;                  // product terms
     static constexpr int ROWB = KC * 2;                            // bytes per operand row and stage
     static constexpr int KSTEPS = KC / 16;                         // MFMA k steps per stage
@@ -93,9 +101,11 @@ __device__ __forceinline__ constexpr int term_b(int t) { return t == 1 ? 1 : t =
 using Wide3 = Shape<256, 256, 2, 4, 1, 1, 16, 4, 2>;
 using Medium3 = Shape<256, 128, 2, 2, 2, 1, 16, 3, 2>;
 using Narrow3 = Shape<128, 64, 4, 1, 3, 1, 32, 2, 2>;
-using Wide6 = Shape<256, 256, 2, 4, 1, 1, 16, 3, 3>;
-using Medium6 = Shape<256, 128, 2, 2, 1, 1, 16, 3, 3>;
-using Narrow6 = Shape<128, 64, 4, 1, 2, 1, 32, 2, 3>;
+// Six products: FP32 sums over 64 k at most, accumulated in FP64 (64 x 64
+// per wavefront, so the FP64 accumulators fit beside the FP32 ones).
+using Wide6 = Shape<128, 128, 2, 2, 1, 1, 16, 4, 3, 4>;
+using Medium6 = Wide6;
+using Narrow6 = Shape<128, 64, 4, 1, 1, 1, 32, 2, 3, 2>;
 
 // MFMAs spread evenly over the READS fragment reads that follow the first
 // group: slot r gets floor((r+1) M / R) - floor(r M / R) MFMAs, then one read.
@@ -314,6 +324,21 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
         for (int cb = 0; cb < S::CB; ++cb)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.0f;
+    constexpr bool ACC64 = S::FL > 0;
+    double acc64[ACC64 ? S::RB : 1][ACC64 ? S::CB : 1][16];
+    if constexpr (ACC64) {
+#pragma unroll
+        for (int rb = 0; rb < S::RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < S::CB; ++cb)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc64[rb][cb][e] = 0.0;
+    }
+    // The value of the update at accumulator element e of block (rb, cb).
+    auto acc_value = [&](int rb, int cb, int e) -> double {
+        if constexpr (ACC64) return acc64[rb][cb][e];
+        return (double)acc[rb][cb][e];
+    };
 
     // Epilogue geometry (see the accumulator layout below): tile-relative row
     // i, column j; stored iff i < rlim, j < clim and (lower part) i - j >= dd.
@@ -390,7 +415,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
-                    buf_store_c<T>(cv[h][e] - (double)acc[rb][c2 + h][e], crs, vo,
+                    buf_store_c<T>(cv[h][e] - acc_value(rb, c2 + h, e), crs, vo,
                                    (int)(ju * lda * (int64_t)sizeof(T)));
                 }
             return;
@@ -401,7 +426,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int ju = (c2 + h) * 32 + 8 * (e >> 2) + (e & 3);
-                if (c_ok(rb, ju)) p0[ju * lda] = (T)(cv[h][e] - (double)acc[rb][c2 + h][e]);
+                if (c_ok(rb, ju)) p0[ju * lda] = (T)(cv[h][e] - acc_value(rb, c2 + h, e));
             }
     };
 
@@ -491,6 +516,21 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             }
             __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - rest, 0);
+        }
+        if constexpr (ACC64) {
+            // Every FL stages (and after the last) the FP32 sums move into
+            // the FP64 accumulators and restart from zero.
+            if ((st + 1) % S::FL == 0 || st == nstages - 1) {
+#pragma unroll
+                for (int rb = 0; rb < S::RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < S::CB; ++cb)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) {
+                            acc64[rb][cb][e] += (double)acc[rb][cb][e];
+                            acc[rb][cb][e] = 0.0f;
+                        }
+            }
         }
     }
 
