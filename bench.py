@@ -499,17 +499,23 @@ def bench_lensemble(torch, B, W, dev, count=4096):
         us[i].copy_(torch.from_numpy(W.uniform_stream(int(ns[i]), seed=4000 + i)))
     torch.cuda.synchronize()
     flops = float(np.sum(ns.astype(np.float64) ** 3) / 3.0)
+    # Compulsory HBM bytes of the call: each kernel's lower triangle read once
+    # (FP32) and the factor's written once.
+    nsf = ns.astype(np.float64)
+    compulsory = float(np.sum(nsf * (nsf + 1) / 2) * 4 * 2)
     out = {"workload": f"{count} L-ensemble marginal kernels K = L(L+I)^-1, L = diag(q) Phi Phi^T diag(q), "
                        "Phi n_i x 64 ~ N(0, 1/64), q ~ LogNormal(0, 0.5), n_i ~ U{64..1024}; formed in "
                        "FP64, stored FP32; one sample each in one batched LDL^H call",
-           "count": count, "sum_n": int(ns.sum()), "flops_per_call": flops}
+           "count": count, "sum_n": int(ns.sum()), "flops_per_call": flops,
+           "compulsory_bytes": compulsory, "hbm_floor_ms": round(compulsory / PEAK_HBM * 1e3, 4)}
     mflat = torch.empty(int(uoffs[-1]), dtype=torch.uint8, device=dev)
     pflat = torch.empty(int(uoffs[-1]), dtype=torch.float64, device=dev)
     lls = torch.empty(count, dtype=torch.float64, device=dev)
     infos = torch.empty(count, dtype=torch.int32, device=dev)
     outs = [{"mask": mflat[int(uoffs[i]):int(uoffs[i + 1])], "pivots": pflat[int(uoffs[i]):int(uoffs[i + 1])],
              "loglik": lls[i:i + 1], "info": infos[i:i + 1]} for i in range(count)]
-    for name, prec in (("split", B.DPP_PREC_SPLIT_BF16), ("fp64", B.DPP_PREC_FP64)):
+    for name, prec in (("split6", B.DPP_PREC_SPLIT_BF16X6), ("split", B.DPP_PREC_SPLIT_BF16),
+                       ("fp64", B.DPP_PREC_FP64)):
         ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F32, [int(x) for x in ns], prec),
                          dtype=torch.uint8, device=dev)
 
@@ -522,6 +528,7 @@ def bench_lensemble(torch, B, W, dev, count=4096):
         ms_eager = eager_time(torch, step, reps=3)
         sizes = np.array([int(x) for x in torch.stack([o["mask"].sum() for o in outs]).cpu()])
         out[name] = {"ms_per_call": round(ms, 3), "samples_per_s": round(count / (ms * 1e-3), 1),
+                     "frac_of_hbm_floor": round(compulsory / PEAK_HBM * 1e3 / ms, 4),
                      "eager_ms_per_call": round(ms_eager, 3),
                      "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
                      "info_all_zero": bool((infos == 0).all().item()),

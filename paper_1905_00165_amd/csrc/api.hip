@@ -31,6 +31,7 @@
 
 #include "dpp.h"
 #include "dpp_internal.h"
+#include "tuning.h"
 
 namespace {
 
@@ -63,8 +64,8 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     // (n - j1)^2 per trailing update; B0 = 512 balances them at n = 8192.
     // A complex column is two real columns of the products' real forms, so
     // complex panels are half as wide for the same real panel width.
-    if (herm) p.B0 = p.pieces ? 4096 : 2048;
-    else p.B0 = 512;
+    if (herm) p.B0 = p.pieces ? dpp::tuned::kB0LdlhSplit : dpp::tuned::kB0LdlhFp64;
+    else p.B0 = dpp::tuned::kB0Lu;
     if (p.cplx) p.B0 /= 2;
     // The split copies hold the columns of one outer panel, at most B0 and no
     // more than the largest problem has (rounded to whole blocks), so small
@@ -127,12 +128,12 @@ dpp_status device_ok()
 // Kernel families whose launches the profiler tells apart.
 enum KernelId {
     K_LEAF_LDLH, K_LEAF_LU, K_LEAF_ZLDLH, K_LEAF_ZLU, K_UPDATE_F64, K_UPDATE_BF16X3,
-    K_UPDATE_BF16X6, K_STORE_DIAG, K_FINALIZE, K_DESCS, K_COUNT
+    K_UPDATE_BF16X6, K_SMALL_LDLH, K_STORE_DIAG, K_FINALIZE, K_DESCS, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"leaf_ldlh",     "leaf_lu",       "leaf_zldlh",
                                            "leaf_zlu",      "update_f64",    "update_bf16x3",
-                                           "update_bf16x6", "store_diag",    "finalize",
-                                           "store_descs"};
+                                           "update_bf16x6", "small_ldlh",    "store_diag",
+                                           "finalize",      "store_descs"};
 
 struct ProfRecord {
     int id;
@@ -163,14 +164,18 @@ Profiler& prof()
     return p;
 }
 
+// The launches of a batch: every launch covers the size groups in `spans`
+// (problems indexed in `probs`, the whole batch's descriptors).
 struct Ctx {
     Plan plan;
     const DevProb* probs;  // device
-    int count;
+    const dpp::GroupSpan* spans;
+    int nspan;
+    int64_t pfirst, count;  // the problems the spans cover: [pfirst, pfirst + count)
     int64_t nmax;
     int64_t pmax;          // largest npiv: no diagonal block at or past it is decided
     hipStream_t s;
-    const std::vector<int64_t>* ns;  // host copy of the problem sizes
+    const std::vector<int64_t>* ns;  // host copy of the sizes of those problems
     bool profiling;
 };
 
@@ -246,10 +251,10 @@ dpp_status update(const Ctx& c, const dpp::Region& rg, int64_t k0, int kw, int64
     if (c.plan.pieces)
         return timed(c, c.plan.pieces == 2 ? K_UPDATE_BF16X3 : K_UPDATE_BF16X6, fl, by, [&] {
             return dpp::launch_update_split(c.plan.herm, c.plan.dtype, c.plan.pieces, c.probs,
-                                            c.count, c.nmax, rg, k0, kw, j0, c.plan.ss, c.s);
+                                            c.spans, c.nspan, rg, k0, kw, j0, c.plan.ss, c.s);
         });
     return timed(c, K_UPDATE_F64, fl, by, [&] {
-        return dpp::launch_update_f64(c.plan.herm, c.plan.dtype, c.probs, c.count, c.nmax, rg,
+        return dpp::launch_update_f64(c.plan.herm, c.plan.dtype, c.probs, c.spans, c.nspan, rg,
                                       k0, kw, c.s);
     });
 }
@@ -260,16 +265,16 @@ dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
     if (c.profiling) leaf_work(c, c0, fl, by);
     if (c.plan.cplx)
         return timed(c, c.plan.herm ? K_LEAF_ZLDLH : K_LEAF_ZLU, fl, by, [&] {
-            return dpp::launch_leaf_complex(c.plan.herm, c.plan.pieces, c.probs, c.count, c.nmax,
+            return dpp::launch_leaf_complex(c.plan.herm, c.plan.pieces, c.probs, c.spans, c.nspan,
                                             c0, j0, c.plan.ss, c.s);
         });
     if (c.plan.herm)
         return timed(c, K_LEAF_LDLH, fl, by, [&] {
-            return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.pieces, c.probs, c.count, c.nmax, c0,
+            return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.pieces, c.probs, c.spans, c.nspan, c0,
                                          j0, c.plan.ss, c.s);
         });
     return timed(c, K_LEAF_LU, fl, by, [&] {
-        return dpp::launch_leaf_lu(c.plan.dtype, c.plan.pieces, c.probs, c.count, c.nmax, c0, j0,
+        return dpp::launch_leaf_lu(c.plan.dtype, c.plan.pieces, c.probs, c.spans, c.nspan, c0, j0,
                                    c.plan.ss, c.s);
     });
 }
@@ -316,11 +321,18 @@ dpp_status lu_panel(const Ctx& c, int64_t j0)
     return DPP_OK;
 }
 
-// Size groups of a batch: widths of 128 up to n = 2048, then of 1024.
-int64_t size_group(int64_t n) { return n <= 2048 ? (n + 127) / 128 : 16 + (n + 1023) / 1024; }
+// Size groups of a batch (tuning.h): narrow widths up to kGroupSplitN, then wide.
+int64_t size_group(int64_t n)
+{
+    using namespace dpp::tuned;
+    const int64_t narrow = (kGroupSplitN + kGroupNarrow - 1) / kGroupNarrow;
+    return n <= kGroupSplitN ? (n + kGroupNarrow - 1) / kGroupNarrow
+                             : narrow + (n + kGroupWide - 1) / kGroupWide;
+}
 
-// The launch sequence of one group of problems (descriptors c.probs[0, c.count)).
-dpp_status run_group(const Ctx& c)
+// The launch sequence of the problems the spans cover: one fixed sequence for
+// the largest n, each launch covering every size group that has its step.
+dpp_status run_groups(const Ctx& c)
 {
     const Plan& plan = c.plan;
     for (int64_t j0 = 0; j0 < c.pmax; j0 += plan.B0) {
@@ -333,10 +345,12 @@ dpp_status run_group(const Ctx& c)
         }
     }
     dpp_status st = timed(c, K_STORE_DIAG, 0.0, 0.0, [&] {
-        return dpp::launch_store_diag(plan.herm, plan.dtype, c.probs, c.count, c.nmax, c.s);
+        return dpp::launch_store_diag(plan.herm, plan.dtype, c.probs + c.pfirst, (int)c.count, c.nmax,
+                                      c.s);
     });
     if (st != DPP_OK) return st;
-    return timed(c, K_FINALIZE, 0.0, 0.0, [&] { return dpp::launch_finalize(c.probs, c.count, c.s); });
+    return timed(c, K_FINALIZE, 0.0, 0.0,
+                 [&] { return dpp::launch_finalize(c.probs + c.pfirst, (int)c.count, c.s); });
 }
 
 // An out-of-place problem's K: a valid leading dimension, and either A itself
@@ -379,11 +393,13 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     const dpp_status dev = device_ok();
     if (dev != DPP_OK) return dev;
 
-    // Problems sorted by size (stable) and cut into groups of similar n; each
-    // group runs its own launch sequence sized for its largest n, so small
-    // problems of a mixed batch do not ride in grids sized for the largest.
-    // The blocking never depends on the other sizes, so the grouping changes
-    // no result.
+    // Problems sorted by size (stable) and cut into groups of similar n. All
+    // groups run one launch sequence (the one of the largest n); in each
+    // launch a group gets workgroups sized for its own largest n (and, for
+    // the updates, a tile shape for its own column count), so small problems
+    // do not ride in grids sized for the largest, and the number of launches
+    // does not grow with the number of groups. The blocking never depends on
+    // the other sizes, so the grouping changes no result.
     std::vector<int64_t> order((size_t)count);
     for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -424,7 +440,8 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     }
     std::vector<int64_t> ns_all((size_t)count);
     for (int64_t p = 0; p < count; ++p) ns_all[(size_t)p] = host[(size_t)p].n;
-    Ctx c{plan, static_cast<const DevProb*>(ws), (int)count, nmax, nmax, s, &ns_all, profiling};
+    Ctx c{plan, static_cast<const DevProb*>(ws), nullptr, 0, 0, count, nmax, nmax, s, &ns_all,
+          profiling};
 
     // Descriptors reach the device as kernel arguments (copied at launch), so
     // the call neither reads host memory later nor blocks the host.
@@ -436,17 +453,46 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         if (st != DPP_OK) return st;
     }
 
-    for (int64_t p0 = 0; p0 < count;) {
+    // Small real Hermitian problems (the smallest, at the front of the sorted
+    // order) run whole in LDS, one workgroup each, in one launch.
+    int64_t nsmall = 0;
+    if (plan.herm && !plan.cplx) {
+        const int64_t cut = std::min(dpp::kSmallMax, dpp::tuned::kSmallCutover[plan.pieces ? plan.pieces - 1 : 0]);
+        while (nsmall < count && host[(size_t)nsmall].n <= cut) ++nsmall;
+    }
+    if (nsmall > 0) {
+        const int64_t nm = host[(size_t)(nsmall - 1)].n;
+        const std::vector<int64_t> ns_small(ns_all.begin(), ns_all.begin() + nsmall);
+        const Ctx cs{plan, c.probs, nullptr, 0, 0, nsmall, nm, nm, s, &ns_small, profiling};
+        double fl = 0.0;
+        for (int64_t n : ns_small) fl += (double)n * n * n / 3.0;
+        dpp_status st = timed(cs, K_SMALL_LDLH, fl, 0.0, [&] {
+            return dpp::launch_small_ldlh(plan.dtype, c.probs, (int)nsmall, nm, s);
+        });
+        if (st != DPP_OK) return st;
+        st = timed(cs, K_FINALIZE, 0.0, 0.0, [&] { return dpp::launch_finalize(c.probs, (int)nsmall, s); });
+        if (st != DPP_OK) return st;
+    }
+
+    // Size groups, each sized in its launches for its own largest n; up to
+    // kMaxGroupsPerLaunch of them share every launch.
+    std::vector<dpp::GroupSpan> spans;
+    for (int64_t p0 = nsmall; p0 < count;) {
         int64_t p1 = p0 + 1;
         while (p1 < count && size_group(host[(size_t)p1].n) == size_group(host[(size_t)p0].n)) ++p1;
-        std::vector<int64_t> ns(ns_all.begin() + p0, ns_all.begin() + p1);
-        int64_t pmax = 0;
-        for (int64_t p = p0; p < p1; ++p) pmax = std::max(pmax, host[(size_t)p].npiv);
-        const Ctx g{plan, c.probs + p0, (int)(p1 - p0), host[(size_t)(p1 - 1)].n, pmax, s, &ns,
-                    profiling};
-        const dpp_status st = run_group(g);
-        if (st != DPP_OK) return st;
+        spans.push_back(dpp::GroupSpan{p0, p1 - p0, host[(size_t)(p1 - 1)].n});
         p0 = p1;
+    }
+    for (size_t g0 = 0; g0 < spans.size(); g0 += dpp::kMaxGroupsPerLaunch) {
+        const size_t g1 = std::min(spans.size(), g0 + (size_t)dpp::kMaxGroupsPerLaunch);
+        const int64_t pfirst = spans[g0].p0, plast = spans[g1 - 1].p0 + spans[g1 - 1].count;
+        std::vector<int64_t> ns(ns_all.begin() + pfirst, ns_all.begin() + plast);
+        int64_t pmax = 0;
+        for (int64_t p = pfirst; p < plast; ++p) pmax = std::max(pmax, host[(size_t)p].npiv);
+        const Ctx g{plan, c.probs, spans.data() + g0, (int)(g1 - g0), pfirst, plast - pfirst,
+                    spans[g1 - 1].nmax, pmax, s, &ns, profiling};
+        const dpp_status st = run_groups(g);
+        if (st != DPP_OK) return st;
     }
     return DPP_OK;
 }

@@ -95,23 +95,60 @@ __host__ __device__ inline int64_t plane_off(int64_t r, int kk, int ss)
            (kk & 15);
 }
 
+// ------------------------------------------------------------- size groups
+// A batched call sorts its problems by n and cuts them into size groups; each
+// step of the factorization is then one launch (or, for the updates, one per
+// tile shape) covering every group that has that step. Within a launch group g
+// owns the workgroups [off[g], off[g + 1]): wpp[g] of them for each of its
+// problems [p0[g], p0[g] + (off[g + 1] - off[g]) / wpp[g]), and aux[g] is a
+// per-group parameter of the kernel (the diagonal-block kernels: row groups
+// per wavefront). The map travels in the kernel arguments.
+struct GroupSpan {
+    int64_t p0, count, nmax;  // first problem, problems, largest n of the group
+};
+constexpr int kMaxGroupsPerLaunch = 32;
+struct GroupMap {
+    int ng;
+    int off[kMaxGroupsPerLaunch + 1];
+    int wpp[kMaxGroupsPerLaunch];
+    int p0[kMaxGroupsPerLaunch];
+    int aux[kMaxGroupsPerLaunch];
+};
+// Problem, workgroup within the problem and aux of the launch's workgroup b
+// (uniform across the workgroup); false past the last group.
+__device__ __forceinline__ bool group_slot(const GroupMap& M, int64_t b, int& prob, int& w, int& aux)
+{
+    if (b >= M.off[M.ng]) return false;
+    int g = 0;
+    while (g + 1 < M.ng && b >= M.off[g + 1]) ++g;
+    const int local = (int)(b - M.off[g]);
+    prob = M.p0[g] + local / M.wpp[g];
+    w = local % M.wpp[g];
+    aux = M.aux[g];
+    return true;
+}
+// Workgroup index b of a launch of G workgroups (G a multiple of 8) such that
+// each of the 8 XCDs (workgroup i runs on XCD i % 8) takes a contiguous range.
+__device__ __forceinline__ int64_t xcd_order(int64_t i, int64_t G) { return (i % 8) * (G / 8) + i / 8; }
+
 // ------------------------------------------------------------------ launchers
-// Each returns the launch status; `nprob` problems, grid.y indexes problems.
-// nmax is the largest n in the batch; the kernels clamp per problem.
+// Each returns the launch status. `spans`/`nspan`: the size groups the launch
+// covers (host array, problems indexed in `probs`); the kernels clamp per
+// problem to its own n.
 
 // Diagonal block [c0, c0+64) of every problem: decisions, L11/D1 (or L11/U11),
 // and the panel solves for the rows below it (LU: and the columns to its
 // right). With pieces = 2 or 3 also writes that many split-BF16 pieces of
 // each panel value (0: none) at outer panel offset j0 with row stride ss.
-hipError_t launch_leaf_ldlh(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
-                            int64_t c0, int64_t j0, int ss, hipStream_t s);
-hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
-                          int64_t c0, int64_t j0, int ss, hipStream_t s);
+hipError_t launch_leaf_ldlh(int dtype, int pieces, const DevProb* probs, const GroupSpan* spans,
+                            int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s);
+hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, const GroupSpan* spans,
+                          int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s);
 // Complex kernels (storage dtype 2): the diagonal block [c0, c0 + kLeafC) in
 // complex columns; the split planes hold the real forms L' and W' at real
 // column 2 (c0 - j0) of the outer panel.
-hipError_t launch_leaf_complex(bool herm, int pieces, const DevProb* probs, int nprob,
-                               int64_t nmax, int64_t c0, int64_t j0, int ss, hipStream_t s);
+hipError_t launch_leaf_complex(bool herm, int pieces, const DevProb* probs, const GroupSpan* spans,
+                               int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s);
 
 // Schur-complement update of rows [base, n) x cols [base, min(base+ncols, n))
 // by the K range [k0, k0+kw) of the factored columns; herm: lower part only.
@@ -130,13 +167,24 @@ inline Region trailing_region(int64_t base, int64_t ncols)
 
 // dtype 0: FP64 storage, 1: FP32, 2: complex (FP64 parts; region, k0 and kw
 // in complex rows and columns, the products on the real forms).
-hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
-                             Region rg, int64_t k0, int kw, hipStream_t s);
+hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, const GroupSpan* spans,
+                             int nspan, Region rg, int64_t k0, int kw, hipStream_t s);
 // Split-BF16 form: the products of the `pieces` (2 or 3) BF16 pieces of L and
 // B whose orders sum to at most pieces - 1 (3 or 6 MFMA products).
-hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs, int nprob,
-                               int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
-                               hipStream_t s);
+// Groups whose updated columns call for different tile shapes go to separate
+// launches (at most three).
+hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs,
+                               const GroupSpan* spans, int nspan, Region rg, int64_t k0, int kw,
+                               int64_t j0, int ss, hipStream_t s);
+
+// Small Hermitian real problems (n <= kSmallMax, FP64 or FP32 storage), one
+// workgroup each with the whole lower triangle in LDS (small_ldlh.hip): the
+// decisions, the factor or conditional kernel in A, mask and pivots; loglik
+// and info come from launch_finalize as for the other problems.
+constexpr int64_t kSmallMax = 192;
+size_t small_ldlh_lds_bytes(int64_t n);
+hipError_t launch_small_ldlh(int dtype, const DevProb* probs, int nprob, int64_t nmax,
+                             hipStream_t s);
 
 // loglik (fixed-order sum of ln|piv|) and info, one workgroup per problem.
 hipError_t launch_finalize(const DevProb* probs, int nprob, hipStream_t s);

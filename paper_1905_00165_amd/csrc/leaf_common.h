@@ -74,6 +74,30 @@ inline int groups_per_wave(int64_t rows, int nprob, int per_cu, int* gx)
     return best;
 }
 
+// Group map of one diagonal-block launch at column c0 (block width bw): for
+// each size group that has the block, its workgroups per problem and row
+// groups per wavefront (groups_per_wave, sized as if the group ran alone).
+// Returns the launch's workgroups (0: no group has the block).
+inline int64_t leaf_map(const GroupSpan* spans, int nspan, int64_t c0, int bw, int per_cu,
+                        GroupMap& M)
+{
+    M.ng = 0;
+    M.off[0] = 0;
+    int64_t off = 0;
+    for (int i = 0; i < nspan && M.ng < kMaxGroupsPerLaunch; ++i) {
+        const GroupSpan& g = spans[i];
+        if (c0 >= g.nmax) continue;
+        int gx = 1;
+        const int gpw = groups_per_wave(g.nmax - c0 - bw, (int)g.count, per_cu, &gx);
+        M.p0[M.ng] = (int)g.p0;
+        M.wpp[M.ng] = gx;
+        M.aux[M.ng] = gpw;
+        off += (int64_t)gx * g.count;
+        M.off[++M.ng] = (int)off;
+    }
+    return off;
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);

@@ -95,15 +95,17 @@ __device__ __forceinline__ void lprime_rows(const double (&x)[8], double (&r0)[8
 // lower) on the matrix cores; L21 = W D1^{-1} to A; with NPC pieces the real
 // forms L' and W' to the split planes.
 template <int NPC>
-__global__ __launch_bounds__(kThreads, 2) void leaf_zldlh(const DevProb* __restrict__ probs, int64_t c0,
-                                                    int64_t j0, int ss, int gpw)
+__global__ __launch_bounds__(kThreads, 2) void leaf_zldlh(const DevProb* __restrict__ probs, GroupMap M,
+                                                    int64_t c0, int64_t j0, int ss)
 {
-    const DevProb P = probs[blockIdx.y];
+    int pi, bx, gpw;  // problem, workgroup within it, row groups per wavefront
+    if (!group_slot(M, blockIdx.x, pi, bx, gpw)) return;
+    const DevProb P = probs[pi];
     const int64_t n = P.n;
     if (c0 >= P.npiv) return;
     const int bs = (int)((n - c0) < LC ? (n - c0) : LC);
-    const int64_t row0 = c0 + bs + (int64_t)blockIdx.x * (kWaves * 16 * gpw);
-    if (blockIdx.x > 0 && row0 >= n) return;
+    const int64_t row0 = c0 + bs + (int64_t)bx * (kWaves * 16 * gpw);
+    if (bx > 0 && row0 >= n) return;
 
     cd* __restrict__ A = static_cast<cd*>(P.A);
     const int64_t lda = P.lda;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_zldlh(const DevProb* __restr
                 sL[(2 * t + 1) * LR + 2 * lane + 1] = v.x;
             }
             sR[lane] = lane < bs ? 1.0 / mydp : 1.0;
-            if (blockIdx.x == 0 && lane < bs) {
+            if (bx == 0 && lane < bs) {
                 cd* blk = reinterpret_cast<cd*>(P.diag) + (c0 / LC) * (LC * LC);
 #pragma unroll
                 for (int k = 0; k < LC; ++k) blk[k * LC + lane] = a[k];
@@ -291,15 +293,17 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_zldlh(const DevProb* __restr
 // the wavefront's LDS tile (a complex column segment of 32 entries is the 64
 // real values of its real form, contiguous in memory).
 template <int NPC>
-__global__ __launch_bounds__(kThreads, 1) void leaf_zlu(const DevProb* __restrict__ probs, int64_t c0,
-                                                  int64_t j0, int ss, int gpw)
+__global__ __launch_bounds__(kThreads, 1) void leaf_zlu(const DevProb* __restrict__ probs, GroupMap M,
+                                                  int64_t c0, int64_t j0, int ss)
 {
-    const DevProb P = probs[blockIdx.y];
+    int pi, bx, gpw;  // problem, workgroup within it, row groups per wavefront
+    if (!group_slot(M, blockIdx.x, pi, bx, gpw)) return;
+    const DevProb P = probs[pi];
     const int64_t n = P.n;
     if (c0 >= P.npiv) return;
     const int bs = (int)((n - c0) < LC ? (n - c0) : LC);
-    const int64_t idx0 = c0 + bs + (int64_t)blockIdx.x * (kWaves * 16 * gpw);
-    if (blockIdx.x > 0 && idx0 >= n) return;
+    const int64_t idx0 = c0 + bs + (int64_t)bx * (kWaves * 16 * gpw);
+    if (bx > 0 && idx0 >= n) return;
 
     cd* __restrict__ A = static_cast<cd*>(P.A);
     const int64_t lda = P.lda;
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(kThreads, 1) void leaf_zlu(const DevProb* __restric
 #pragma unroll
             for (int t = 0; t < LC; ++t)
                 sC[t * LC + lane] = lane < bs ? a[t] : (t == lane ? cd{1.0, 0.0} : cd{0.0, 0.0});
-            if (blockIdx.x == 0 && lane < bs) {
+            if (bx == 0 && lane < bs) {
                 cd* blk = reinterpret_cast<cd*>(P.diag) + (c0 / LC) * (LC * LC);
 #pragma unroll
                 for (int k = 0; k < LC; ++k) blk[k * LC + lane] = a[k];
@@ -568,25 +572,27 @@ __global__ __launch_bounds__(kThreads, 1) void leaf_zlu(const DevProb* __restric
 }
 
 template <int NPC>
-hipError_t launch_z(bool herm, const DevProb* probs, int nprob, int64_t nmax, int64_t c0, int64_t j0,
-                    int ss, hipStream_t s)
+hipError_t launch_z(bool herm, const DevProb* probs, const GroupSpan* spans, int nspan, int64_t c0,
+                    int64_t j0, int ss, hipStream_t s)
 {
-    int gx = 1;
-    const int gpw = groups_per_wave(nmax - c0 - LC, nprob, herm ? 2 : 1, &gx);
-    dim3 grid(gx, nprob), block(kThreads);
-    if (herm) hipLaunchKernelGGL((leaf_zldlh<NPC>), grid, block, 0, s, probs, c0, j0, ss, gpw);
-    else hipLaunchKernelGGL((leaf_zlu<NPC>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    GroupMap M;
+    const int64_t total = leaf_map(spans, nspan, c0, LC, herm ? 2 : 1, M);
+    if (total == 0) return hipSuccess;
+    dim3 grid((unsigned)total), block(kThreads);
+    if (herm) hipLaunchKernelGGL((leaf_zldlh<NPC>), grid, block, 0, s, probs, M, c0, j0, ss);
+    else hipLaunchKernelGGL((leaf_zlu<NPC>), grid, block, 0, s, probs, M, c0, j0, ss);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_leaf_complex(bool herm, int pieces, const DevProb* probs, int nprob, int64_t nmax,
-                               int64_t c0, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_leaf_complex(bool herm, int pieces, const DevProb* probs, const GroupSpan* spans,
+                               int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s)
 {
-    if (pieces == 3) return launch_z<3>(herm, probs, nprob, nmax, c0, j0, ss, s);
-    if (pieces == 2) return launch_z<2>(herm, probs, nprob, nmax, c0, j0, ss, s);
-    if (pieces == 0) return launch_z<0>(herm, probs, nprob, nmax, c0, j0, ss, s);
+    if (nspan > kMaxGroupsPerLaunch) return hipErrorInvalidValue;
+    if (pieces == 3) return launch_z<3>(herm, probs, spans, nspan, c0, j0, ss, s);
+    if (pieces == 2) return launch_z<2>(herm, probs, spans, nspan, c0, j0, ss, s);
+    if (pieces == 0) return launch_z<0>(herm, probs, spans, nspan, c0, j0, ss, s);
     return hipErrorInvalidValue;
 }
 

@@ -37,15 +37,17 @@ using namespace leaf;
 constexpr int kLP = L + 1;
 
 template <typename T, int NPC>
-__global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict__ probs, int64_t c0,
-                                             int64_t j0, int ss, int gpw)
+__global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict__ probs, GroupMap M,
+                                             int64_t c0, int64_t j0, int ss)
 {
-    const DevProb P = probs[blockIdx.y];
+    int pi, bx, gpw;  // problem, workgroup within it, row groups per wavefront
+    if (!group_slot(M, blockIdx.x, pi, bx, gpw)) return;
+    const DevProb P = probs[pi];
     const int64_t n = P.n;
     if (c0 >= P.npiv) return;  // npiv <= n: only the first npiv indices are decided
     const int bs = (int)((n - c0) < L ? (n - c0) : L);
-    const int64_t idx0 = c0 + bs + (int64_t)blockIdx.x * (kWaves * 16 * gpw);
-    if (blockIdx.x > 0 && idx0 >= n) return;
+    const int64_t idx0 = c0 + bs + (int64_t)bx * (kWaves * 16 * gpw);
+    if (bx > 0 && idx0 >= n) return;
 
     T* __restrict__ A = static_cast<T*>(P.A);
     const int64_t lda = P.lda;
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict
         // workgroups of this launch may still be loading the original block
         // from A for their own copy of the chain. A later launch copies the
         // strip into A (no kernel reads the diagonal blocks from A).
-        if (blockIdx.x == 0 && lane < bs) {
+        if (bx == 0 && lane < bs) {
             double* blk = P.diag + (c0 / L) * (L * L);
 #pragma unroll
             for (int k = 0; k < L; ++k) blk[k * L + lane] = a[k];
@@ -265,28 +267,30 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict
 }
 
 template <typename T>
-hipError_t launch_t(int pieces, const DevProb* probs, int nprob, int64_t nmax, int64_t c0,
+hipError_t launch_t(int pieces, const DevProb* probs, const GroupSpan* spans, int nspan, int64_t c0,
                     int64_t j0, int ss, hipStream_t s)
 {
-    int gx = 1;
     // Sized for one workgroup per CU: sizing for two (half the row groups per
     // wavefront, twice the redundant chains) measured slower.
-    const int gpw = groups_per_wave(nmax - c0 - L, nprob, 1, &gx);
-    dim3 grid(gx, nprob), block(kThreads);
-    if (pieces == 3) hipLaunchKernelGGL((leaf_lu<T, 3>), grid, block, 0, s, probs, c0, j0, ss, gpw);
-    else if (pieces == 2) hipLaunchKernelGGL((leaf_lu<T, 2>), grid, block, 0, s, probs, c0, j0, ss, gpw);
-    else hipLaunchKernelGGL((leaf_lu<T, 0>), grid, block, 0, s, probs, c0, j0, ss, gpw);
+    GroupMap M;
+    const int64_t total = leaf_map(spans, nspan, c0, L, 1, M);
+    if (total == 0) return hipSuccess;
+    dim3 grid((unsigned)total), block(kThreads);
+    if (pieces == 3) hipLaunchKernelGGL((leaf_lu<T, 3>), grid, block, 0, s, probs, M, c0, j0, ss);
+    else if (pieces == 2) hipLaunchKernelGGL((leaf_lu<T, 2>), grid, block, 0, s, probs, M, c0, j0, ss);
+    else hipLaunchKernelGGL((leaf_lu<T, 0>), grid, block, 0, s, probs, M, c0, j0, ss);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, int nprob, int64_t nmax,
-                          int64_t c0, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, const GroupSpan* spans,
+                          int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s)
 {
     if (pieces != 0 && pieces != 2 && pieces != 3) return hipErrorInvalidValue;
-    if (dtype == 0) return launch_t<double>(pieces, probs, nprob, nmax, c0, j0, ss, s);
-    return launch_t<float>(pieces, probs, nprob, nmax, c0, j0, ss, s);
+    if (nspan > kMaxGroupsPerLaunch) return hipErrorInvalidValue;
+    if (dtype == 0) return launch_t<double>(pieces, probs, spans, nspan, c0, j0, ss, s);
+    return launch_t<float>(pieces, probs, spans, nspan, c0, j0, ss, s);
 }
 
 }  // namespace dpp

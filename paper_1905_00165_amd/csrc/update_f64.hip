@@ -16,8 +16,10 @@
 // of 16 staged through two LDS buffers (k-major, so the column-major source is
 // read with unit stride); the next chunk's loads are in flight while the
 // current one is multiplied. For LDL^H only tiles on or below the diagonal are launched.
-// Workgroup b runs tile (b % 8) * (G / 8) + b / 8 (G, the grid size, is a
-// multiple of 8), so each XCD takes a contiguous range of tiles.
+// One launch covers the problems of several size groups (GroupMap): workgroup
+// b takes slot (b % 8) * (G / 8) + b / 8 of the launch (G, the grid size, is a
+// multiple of 8), so each XCD takes a contiguous range of tiles, and the slot
+// names a problem and one of its tiles.
 //
 // Complex kernels (CPLX) run the same product on the real forms of the
 // factors (dpp_internal.h): a tile is 128 real rows of C' (64 complex rows)
@@ -82,12 +84,16 @@ __device__ __forceinline__ void gstore(T* p, double v)
 }
 
 template <typename T, bool HERM, bool CPLX>
-__global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__ probs, Region rg,
-                                                  int64_t k0, int kw)
+__global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__ probs, GroupMap M,
+                                                  Region rg, int64_t k0, int kw)
 {
     static_assert(!CPLX || sizeof(T) == 8, "complex storage: FP64 parts");
     constexpr int RS = CPLX ? 2 : 1;  // real rows of C per row of the region
-    const DevProb P = probs[blockIdx.y];
+    // XCD-contiguous order over the launch (grid size a multiple of 8), then
+    // the problem and its tile.
+    int pi, tw, unused;
+    if (!group_slot(M, xcd_order(blockIdx.x, gridDim.x), pi, tw, unused)) return;
+    const DevProb P = probs[pi];
     const int64_t n = P.n;
     const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
     const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
@@ -96,9 +102,7 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     // Only decided columns contribute: k in [k0, min(k0 + kw, npiv)).
     if (k0 + kw > P.npiv) kw = (int)(P.npiv - k0);
     const int64_t NR = (nrows * RS + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
-    // XCD-contiguous tile order (grid size is a multiple of 8).
-    const int64_t per_xcd = gridDim.x / 8;
-    const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t t = tw;
     TileCoord tc;
     if (!tile_of(t, NR, NC, HERM && !CPLX, tc)) return;
     // Complex Hermitian: skip tiles entirely above the diagonal.
@@ -308,27 +312,40 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
 
 }  // namespace
 
-hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nmax,
-                             Region rg, int64_t k0, int kw, hipStream_t s)
+hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, const GroupSpan* spans,
+                             int nspan, Region rg, int64_t k0, int kw, hipStream_t s)
 {
-    const int64_t nrows = (rg.r0 + rg.rlen < nmax ? rg.r0 + rg.rlen : nmax) - rg.r0;
-    const int64_t nc = (rg.c0 + rg.clen < nmax ? rg.c0 + rg.clen : nmax) - rg.c0;
-    if (nrows <= 0 || nc <= 0) return hipSuccess;
     if (herm && rg.r0 != rg.c0) return hipErrorInvalidValue;
     const bool cplx = dtype == 2;
-    if (kw % (cplx ? KC / 2 : KC) != 0) return hipErrorInvalidValue;
-    const int64_t NR = (nrows * (cplx ? 2 : 1) + TM - 1) / TM, NC = (nc + TN - 1) / TN;
-    const int64_t tiles = herm && !cplx ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
-    dim3 grid((unsigned)((tiles + 7) / 8 * 8), nprob), block(256);
+    if (kw % (cplx ? KC / 2 : KC) != 0 || nspan > kMaxGroupsPerLaunch) return hipErrorInvalidValue;
+    GroupMap M;
+    M.ng = 0;
+    M.off[0] = 0;
+    int64_t total = 0;
+    for (int i = 0; i < nspan; ++i) {
+        const GroupSpan& g = spans[i];
+        const int64_t nrows = (rg.r0 + rg.rlen < g.nmax ? rg.r0 + rg.rlen : g.nmax) - rg.r0;
+        const int64_t nc = (rg.c0 + rg.clen < g.nmax ? rg.c0 + rg.clen : g.nmax) - rg.c0;
+        if (nrows <= 0 || nc <= 0 || k0 + kw > g.nmax) continue;
+        const int64_t NR = (nrows * (cplx ? 2 : 1) + TM - 1) / TM, NC = (nc + TN - 1) / TN;
+        const int64_t tiles = herm && !cplx ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
+        M.p0[M.ng] = (int)g.p0;
+        M.wpp[M.ng] = (int)tiles;
+        M.aux[M.ng] = 0;
+        total += tiles * g.count;
+        M.off[++M.ng] = (int)total;
+    }
+    if (total == 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 7) / 8 * 8)), block(256);
     if (cplx) {
-        if (herm) hipLaunchKernelGGL((update_f64<double, true, true>), grid, block, 0, s, probs, rg, k0, kw);
-        else hipLaunchKernelGGL((update_f64<double, false, true>), grid, block, 0, s, probs, rg, k0, kw);
+        if (herm) hipLaunchKernelGGL((update_f64<double, true, true>), grid, block, 0, s, probs, M, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<double, false, true>), grid, block, 0, s, probs, M, rg, k0, kw);
     } else if (herm) {
-        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true, false>), grid, block, 0, s, probs, rg, k0, kw);
-        else hipLaunchKernelGGL((update_f64<float, true, false>), grid, block, 0, s, probs, rg, k0, kw);
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true, false>), grid, block, 0, s, probs, M, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, true, false>), grid, block, 0, s, probs, M, rg, k0, kw);
     } else {
-        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false, false>), grid, block, 0, s, probs, rg, k0, kw);
-        else hipLaunchKernelGGL((update_f64<float, false, false>), grid, block, 0, s, probs, rg, k0, kw);
+        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false, false>), grid, block, 0, s, probs, M, rg, k0, kw);
+        else hipLaunchKernelGGL((update_f64<float, false, false>), grid, block, 0, s, probs, M, rg, k0, kw);
     }
     return hipGetLastError();
 }

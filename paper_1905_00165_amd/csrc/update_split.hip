@@ -38,8 +38,10 @@
 // read-modify-write of column-major C is coalesced. Operand rows past the end
 // of the region are read from the last valid row instead: they only feed
 // accumulators that are never stored.
-// Workgroup b runs tile (b % 8) * (G / 8) + b / 8 (G the grid size, a multiple
-// of 8): the 8 XCDs each take a contiguous range of tiles. In the wide shape
+// One launch covers the problems of several size groups (GroupMap): workgroup
+// b takes slot (b % 8) * (G / 8) + b / 8 of the launch (G the grid size, a
+// multiple of 8), so the 8 XCDs each take a contiguous range of tiles, and the
+// slot names a problem and one of its tiles. In the wide shape
 // tiles are ordered by groups of 4 tile columns, row by row within a group, so
 // the ~32 tiles an XCD runs at once form an 8x4 block that shares 8 row panels
 // and 4 column panels in that XCD's L2.
@@ -239,11 +241,16 @@ __device__ __forceinline__ bool grouped_tile(int64_t t, int64_t NR, int64_t NC, 
 // rows of C' (two per complex row) and the real k of the planes (two per
 // complex column), dpp_internal.h.
 template <typename T, bool HERM, class S, bool CPLX>
-__device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, Region rg, int64_t k0,
-                                            int kw, int64_t j0, int ss, unsigned char* lds)
+__device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, const GroupMap& M,
+                                            Region rg, int64_t k0, int kw, int64_t j0, int ss,
+                                            unsigned char* lds)
 {
     constexpr int RS = CPLX ? 2 : 1;  // real rows (and real k) per complex one
-    const DevProb P = probs[blockIdx.y];
+    // XCD-contiguous order over the launch (grid size a multiple of 8), then
+    // the problem and its tile.
+    int pi, tw, unused;
+    if (!group_slot(M, xcd_order(blockIdx.x, gridDim.x), pi, tw, unused)) return;
+    const DevProb P = probs[pi];
     const int64_t n = P.n;
     const int64_t rEndC = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
     const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
@@ -252,8 +259,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
     // Only decided columns contribute: k in [k0, min(k0 + kw, npiv)).
     const int kwp = RS * (k0 + kw <= P.npiv ? kw : (int)(P.npiv - k0));
     const int64_t NR = (nrows * RS + S::TM - 1) / S::TM, NC = (ncols + S::TN - 1) / S::TN;
-    const int64_t per_xcd = gridDim.x / 8;
-    const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t t = tw;
     TileCoord tc;
     if constexpr (S::TM == S::TN) {
         if (!grouped_tile(t, NR, NC, HERM && !CPLX, tc)) return;
@@ -554,21 +560,21 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, R
 // The two product forms as separate kernels, so that profiles tell them apart.
 template <typename T, bool HERM, class S, bool CPLX>
 __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevProb* __restrict__ probs,
-                                                                     Region rg, int64_t k0, int kw,
-                                                                     int64_t j0, int ss)
+                                                                     GroupMap M, Region rg, int64_t k0,
+                                                                     int kw, int64_t j0, int ss)
 {
     static_assert(S::NP == 2, "three products from two pieces");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    update_body<T, HERM, S, CPLX>(probs, rg, k0, kw, j0, ss, lds);
+    update_body<T, HERM, S, CPLX>(probs, M, rg, k0, kw, j0, ss, lds);
 }
 template <typename T, bool HERM, class S, bool CPLX>
 __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x6(const DevProb* __restrict__ probs,
-                                                                     Region rg, int64_t k0, int kw,
-                                                                     int64_t j0, int ss)
+                                                                     GroupMap M, Region rg, int64_t k0,
+                                                                     int kw, int64_t j0, int ss)
 {
     static_assert(S::NP == 3, "six products from three pieces");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    update_body<T, HERM, S, CPLX>(probs, rg, k0, kw, j0, ss, lds);
+    update_body<T, HERM, S, CPLX>(probs, M, rg, k0, kw, j0, ss, lds);
 }
 
 template <typename T, bool HERM, class S, bool CPLX>
@@ -579,12 +585,27 @@ constexpr auto kernel_of()
 }
 
 template <typename T, bool HERM, class S, bool CPLX>
-hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, Region rg,
+hipError_t launch_shape(const DevProb* probs, const GroupSpan* spans, int nspan, Region rg,
                         int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
-    const int64_t NR = (nrows * (CPLX ? 2 : 1) + S::TM - 1) / S::TM, NC = (nc + S::TN - 1) / S::TN;
-    const int64_t tiles = (HERM && !CPLX && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
-    const unsigned grid_x = (unsigned)((tiles + 7) / 8 * 8);  // XCD remap needs a multiple of 8
+    GroupMap M;
+    M.ng = 0;
+    M.off[0] = 0;
+    int64_t total = 0;
+    for (int i = 0; i < nspan; ++i) {
+        const GroupSpan& g = spans[i];
+        const int64_t nrows = (rg.r0 + rg.rlen < g.nmax ? rg.r0 + rg.rlen : g.nmax) - rg.r0;
+        const int64_t nc = (rg.c0 + rg.clen < g.nmax ? rg.c0 + rg.clen : g.nmax) - rg.c0;
+        const int64_t NR = (nrows * (CPLX ? 2 : 1) + S::TM - 1) / S::TM, NC = (nc + S::TN - 1) / S::TN;
+        const int64_t tiles = (HERM && !CPLX && S::TM == S::TN) ? NC * NR - NC * (NC - 1) / 2 : NR * NC;
+        M.p0[M.ng] = (int)g.p0;
+        M.wpp[M.ng] = (int)tiles;
+        M.aux[M.ng] = 0;
+        total += tiles * g.count;
+        M.off[++M.ng] = (int)total;
+    }
+    if (total == 0) return hipSuccess;
+    const unsigned grid_x = (unsigned)((total + 7) / 8 * 8);  // XCD order needs a multiple of 8
     const auto k = kernel_of<T, HERM, S, CPLX>();
     // The dynamic-LDS limit is a per-device function attribute: set it once
     // on each device the kernel runs on.
@@ -598,56 +619,66 @@ hipError_t launch_shape(const DevProb* probs, int nprob, int64_t nrows, int64_t 
         if (e != hipSuccess) return e;
         attr_set.fetch_or(bit);
     }
-    hipLaunchKernelGGL(k, dim3(grid_x, nprob), dim3(S::THREADS), S::LDS, s, probs, rg, k0, kw, j0,
-                       ss);
+    hipLaunchKernelGGL(k, dim3(grid_x), dim3(S::THREADS), S::LDS, s, probs, M, rg, k0, kw, j0, ss);
     return hipGetLastError();
 }
 
+// The tile shape follows the width of each group's updated column range;
+// groups of one shape share a launch.
 template <typename T, bool HERM, int NP, bool CPLX>
-hipError_t launch_t(const DevProb* probs, int nprob, int64_t nrows, int64_t nc, Region rg,
-                    int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_t(const DevProb* probs, const GroupSpan* spans, int nspan, Region rg, int64_t k0,
+                    int kw, int64_t j0, int ss, hipStream_t s)
 {
     using Narrow = std::conditional_t<NP == 2, Narrow3, Narrow6>;
     using Medium = std::conditional_t<NP == 2, Medium3, Medium6>;
     using Wide = std::conditional_t<NP == 2, Wide3, Wide6>;
-    // The tile shape follows the width of the updated column range.
-    if (nc <= 128)
-        return launch_shape<T, HERM, Narrow, CPLX>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    if (nc <= 256)
-        return launch_shape<T, HERM, Medium, CPLX>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    return launch_shape<T, HERM, Wide, CPLX>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    GroupSpan by[3][kMaxGroupsPerLaunch];
+    int cnt[3] = {0, 0, 0};
+    for (int i = 0; i < nspan; ++i) {
+        const GroupSpan& g = spans[i];
+        const int64_t nrows = (rg.r0 + rg.rlen < g.nmax ? rg.r0 + rg.rlen : g.nmax) - rg.r0;
+        const int64_t nc = (rg.c0 + rg.clen < g.nmax ? rg.c0 + rg.clen : g.nmax) - rg.c0;
+        if (nrows <= 0 || nc <= 0 || k0 + kw > g.nmax) continue;
+        const int shape = nc <= 128 ? 0 : (nc <= 256 ? 1 : 2);
+        by[shape][cnt[shape]++] = g;
+    }
+    hipError_t e = hipSuccess;
+    if (cnt[0]) e = launch_shape<T, HERM, Narrow, CPLX>(probs, by[0], cnt[0], rg, k0, kw, j0, ss, s);
+    if (e == hipSuccess && cnt[1])
+        e = launch_shape<T, HERM, Medium, CPLX>(probs, by[1], cnt[1], rg, k0, kw, j0, ss, s);
+    if (e == hipSuccess && cnt[2])
+        e = launch_shape<T, HERM, Wide, CPLX>(probs, by[2], cnt[2], rg, k0, kw, j0, ss, s);
+    return e;
 }
 
 template <int NP>
-hipError_t launch_np(bool herm, int dtype, const DevProb* probs, int nprob, int64_t nrows,
-                     int64_t nc, Region rg, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_np(bool herm, int dtype, const DevProb* probs, const GroupSpan* spans, int nspan,
+                     Region rg, int64_t k0, int kw, int64_t j0, int ss, hipStream_t s)
 {
     if (dtype == 2) {
-        if (herm) return launch_t<double, true, NP, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-        return launch_t<double, false, NP, true>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        if (herm) return launch_t<double, true, NP, true>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
+        return launch_t<double, false, NP, true>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
     }
     if (herm) {
-        if (dtype == 0) return launch_t<double, true, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-        return launch_t<float, true, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+        if (dtype == 0) return launch_t<double, true, NP, false>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
+        return launch_t<float, true, NP, false>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
     }
-    if (dtype == 0) return launch_t<double, false, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    return launch_t<float, false, NP, false>(probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    if (dtype == 0) return launch_t<double, false, NP, false>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
+    return launch_t<float, false, NP, false>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
 }
 
 }  // namespace
 
-hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs, int nprob,
-                               int64_t nmax, Region rg, int64_t k0, int kw, int64_t j0, int ss,
-                               hipStream_t s)
+hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs,
+                               const GroupSpan* spans, int nspan, Region rg, int64_t k0, int kw,
+                               int64_t j0, int ss, hipStream_t s)
 {
-    const int64_t nrows = (rg.r0 + rg.rlen < nmax ? rg.r0 + rg.rlen : nmax) - rg.r0;
-    const int64_t nc = (rg.c0 + rg.clen < nmax ? rg.c0 + rg.clen : nmax) - rg.c0;
-    if (nrows <= 0 || nc <= 0) return hipSuccess;
     // Every stage covers kKAlign real k: 32 real or 16 complex columns.
-    if ((kw * (dtype == 2 ? 2 : 1)) % kKAlign != 0 || (herm && rg.r0 != rg.c0))
+    if ((kw * (dtype == 2 ? 2 : 1)) % kKAlign != 0 || (herm && rg.r0 != rg.c0) ||
+        nspan > kMaxGroupsPerLaunch)
         return hipErrorInvalidValue;
-    if (pieces == 2) return launch_np<2>(herm, dtype, probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
-    if (pieces == 3) return launch_np<3>(herm, dtype, probs, nprob, nrows, nc, rg, k0, kw, j0, ss, s);
+    if (pieces == 2) return launch_np<2>(herm, dtype, probs, spans, nspan, rg, k0, kw, j0, ss, s);
+    if (pieces == 3) return launch_np<3>(herm, dtype, probs, spans, nspan, rg, k0, kw, j0, ss, s);
     return hipErrorInvalidValue;
 }
 

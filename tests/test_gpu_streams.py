@@ -118,3 +118,34 @@ def test_two_callers_streams_at_once(B):
     torch.cuda.synchronize()
     for (Ks, us, As, outs), ref in zip(sets, alone):
         assert _equal(_snapshot(As, outs), ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
+def test_launch_count_does_not_grow_with_size_groups(B, herm, prec):
+    """All size groups of a batch share each step's launch: the batch of six
+    size groups issues as many diagonal-block launches as one problem of its
+    largest n alone, and at most three update launches (one per tile shape)
+    where that problem issues one; Hermitian problems at or below the small
+    cutover take one launch of their own."""
+    Ks, us, As, outs = _problems(B, 11, herm)
+    fb = B.dpp_sample_ldlh_batched if herm else B.dpp_sample_lu_batched
+    B.dpp_profile_begin()
+    fb(As, us, prec=prec, outs=outs, Ks=Ks)
+    batch = B.dpp_profile_end()
+    big = max(range(len(NS)), key=lambda i: NS[i])
+    B.dpp_profile_begin()
+    fb([As[big]], [us[big]], prec=prec, Ks=[Ks[big]])
+    single = B.dpp_profile_end()
+    torch.cuda.synchronize()
+    leaf = "leaf_ldlh" if herm else "leaf_lu"
+    upd = {0: "update_f64", 1: "update_bf16x3", 2: "update_bf16x6"}[prec]
+    print(f"[launches] {'ldlh' if herm else 'lu'} prec={prec}: batch {leaf} {batch[leaf]['launches']} "
+          f"{upd} {batch[upd]['launches']}; single n={NS[big]}: {single[leaf]['launches']} "
+          f"{single[upd]['launches']}")
+    assert batch[leaf]["launches"] == single[leaf]["launches"]
+    assert single[upd]["launches"] <= batch[upd]["launches"] <= 3 * single[upd]["launches"]
+    # one finalize for the blocked problems, one more for the LDS-resident small
+    # ones (Hermitian batches with problems at or below the small cutover)
+    assert batch["store_diag"]["launches"] == 1
+    assert batch["finalize"]["launches"] == 1 + ("small_ldlh" in batch)
