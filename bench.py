@@ -6,6 +6,9 @@ uniform stream (2000 .. 2063), every one of which must have |Y| = r. A step
 samples all 64: `calls` batched LDL^H calls (dpp_sample_ldlh_batched) of
 `batch` samples each, every call reading the resident K and writing each
 sample's factor to a buffer of its own (out of place: no per-sample copy of K).
+By default one call takes all 64 (128 GiB of factors plus the split
+workspace, within one GPU's HBM): the diagonal-block chain, sequential in the
+pivots, then runs once per step for all samples instead of once per call.
 The headline `value` is the samples/s of the split-BF16 path that holds the
 split path's stated tolerance (1e-4 on every pivot) at this size: the
 six-product form (three BF16 pieces per value). The three-product form and
@@ -45,8 +48,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=16384)
     p.add_argument("--rank", type=int, default=4096)
-    p.add_argument("--batch", type=int, default=8, help="samples per batched call")
-    p.add_argument("--calls", type=int, default=8,
+    p.add_argument("--batch", type=int, default=64, help="samples per batched call")
+    p.add_argument("--calls", type=int, default=1,
                    help="batched calls per step (each on its own streams of uniforms)")
     p.add_argument("--prec", choices=["all", "split6", "split", "fp64"], default="all")
     p.add_argument("--cpu-seconds", type=float, default=15.0,

@@ -184,13 +184,18 @@ typedef struct {
  * dpp_sample_ldlh_batched / dpp_sample_lu_batched - `count` independent
  * problems, each with its own n, lda, stream of uniforms and outputs, sampled
  * by one launch sequence on `stream`: the problems are sorted by size into
- * groups, and each step of a group's factorization is one launch covering
- * every problem of the group that still has that step.
+ * groups, and each step of the factorization is one launch covering every
+ * group that has that step (an update: one launch per tile shape). Real
+ * Hermitian problems with n at or below the small-problem cutover instead run
+ * whole in one workgroup each, with FP64 arithmetic at every precision. The
+ * cutover is tuned per precision at build time (0 turns the path off); the
+ * environment variable DPP_SMALL_CUTOVER, read at every call, overrides it
+ * with a value in 0..192 (anything else is ignored).
  *   probs   HOST array of `count` descriptors; it is read before the call
  *           returns and may be reused at once.
  *   ws      device workspace of dpp_workspace_size_batched(...) bytes.
  * Every problem's results equal those of the single call on that problem
- * (bit for bit): the blocking depends only on (dtype, precision), never on
+ * (bit for bit): the blocking depends only on (n, dtype, precision), never on
  * the other problems, and the problems do not interact. Problems must not
  * share A or output buffers.
  */

@@ -15,7 +15,7 @@ kernel objects of the regular build (paper_1905_00165_amd/_build), and a
 fresh process times it through the binding (so every candidate loads its own
 library). Workloads:
 
-  - small-problem cutover: batches of 256 Hermitian kernels of one size n in
+  - small-problem cutover: batches of 1024 Hermitian kernels of one size n in
     {32, 64, ..., 192} (FP32 storage, the L-ensemble construction), with the
     small path everywhere against the blocked path everywhere, per precision;
     the cutover is the largest n below which the small path is faster at
@@ -128,9 +128,27 @@ def _worker(lib, task, arg):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    def graph_timed(step, reps):
+        """ms per replay of one captured call (the host cost of marshalling
+        a large batch stays out of the measurement)."""
+        step()
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        ms = timed(g.replay, reps)
+        del g
+        return ms
+
     res = {}
     if task == "small":
-        n, count = int(arg), 256
+        n, count = int(arg), 1024
         Ks = [W.lensemble_kernel(n, seed=900000 + i, out=torch.empty((n, n), dtype=torch.float32,
                                                                      device=dev).t())
               for i in range(count)]
@@ -139,7 +157,7 @@ def _worker(lib, task, arg):
         for prec in (0, 1, 2):
             ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F32, [n] * count, prec),
                              dtype=torch.uint8, device=dev)
-            res[prec] = timed(lambda: B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, Ks=Ks), 5)
+            res[prec] = graph_timed(lambda: B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, Ks=Ks), 10)
     elif task == "groups":
         count = 4096
         ns = W.lensemble_batch_sizes(count, seed=4)
@@ -151,20 +169,8 @@ def _worker(lib, task, arg):
         for prec in (0, 2):
             ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F32, [int(x) for x in ns], prec),
                              dtype=torch.uint8, device=dev)
-            g = torch.cuda.CUDAGraph()
-            step = lambda: B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, Ks=Ks)
-            step()
-            torch.cuda.synchronize()
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                step()
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            with torch.cuda.graph(g):
-                step()
-            res[prec] = timed(g.replay, 3)
-            del g, ws
+            res[prec] = graph_timed(lambda: B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, Ks=Ks), 3)
+            del ws
     elif task in ("b0_ldlh_split", "b0_ldlh_fp64"):
         n, r, bsz = 16384, 4096, 8
         prec = 2 if task == "b0_ldlh_split" else 0
@@ -212,7 +218,7 @@ def measure(vals, task, arg, log):
     if r.returncode != 0:
         raise RuntimeError(f"worker {task} {arg} failed:\n{r.stderr[-2000:]}")
     out = json.loads(r.stdout.strip().splitlines()[-1])
-    ms = {int(k): v for k, v in out["ms"].items()}
+    ms = {int(k): round(v, 4) for k, v in out["ms"].items()}
     shown = {k: vals[k] for k in ("kSmallCutover", "kGroupNarrow", "kB0LdlhSplit", "kB0LdlhFp64",
                                   "kB0Lu")}
     log(f"[autotune] {task} arg={arg} {shown} -> {ms} ({time.time() - t0:.0f} s)")
@@ -250,7 +256,7 @@ def main():
     for n in sizes:
         on = measure(small_on, "small", n, log)
         off = measure(small_off, "small", n, log)
-        record.append(f"  256 kernels of n = {n}: small path {on}, blocked {off}")
+        record.append(f"  1024 kernels of n = {n}: small path {on}, blocked {off}")
         for p in (0, 1, 2):
             faster[p] = faster[p] and on[p] < off[p]
             if faster[p]:
@@ -284,7 +290,9 @@ def main():
 
     log("[autotune] chosen: " + json.dumps(chosen))
     if a.write:
-        open(TUNING, "w").write(render(chosen, record))
+        text = render(chosen, record)  # reads the current file: before it is truncated
+        with open(TUNING, "w") as f:
+            f.write(text)
         log(f"[autotune] wrote {TUNING}")
     else:
         log("\n".join(record))

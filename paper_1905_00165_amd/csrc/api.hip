@@ -23,6 +23,7 @@
 // a rejected pivot commutes with the outer-product updates (Prop. 5). The
 // sequence depends only on (n, dtype, precision), never on the decisions, so
 // there is no device-to-host traffic inside a call.
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -321,6 +322,19 @@ dpp_status lu_panel(const Ctx& c, int64_t j0)
     return DPP_OK;
 }
 
+// Largest n of the small-problem path: the tuned cutover of the precision,
+// or DPP_SMALL_CUTOVER (a decimal in 0..kSmallMax) when that is set.
+int64_t small_cutover(int pieces)
+{
+    int64_t cut = dpp::tuned::kSmallCutover[pieces ? pieces - 1 : 0];
+    if (const char* e = getenv("DPP_SMALL_CUTOVER")) {
+        char* end = nullptr;
+        const long v = strtol(e, &end, 10);
+        if (end != e && *end == '\0' && v >= 0 && v <= dpp::kSmallMax) cut = v;
+    }
+    return std::min(dpp::kSmallMax, cut);
+}
+
 // Size groups of a batch (tuning.h): narrow widths up to kGroupSplitN, then wide.
 int64_t size_group(int64_t n)
 {
@@ -457,7 +471,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     // order) run whole in LDS, one workgroup each, in one launch.
     int64_t nsmall = 0;
     if (plan.herm && !plan.cplx) {
-        const int64_t cut = std::min(dpp::kSmallMax, dpp::tuned::kSmallCutover[plan.pieces ? plan.pieces - 1 : 0]);
+        const int64_t cut = small_cutover(plan.pieces);
         while (nsmall < count && host[(size_t)nsmall].n <= cut) ++nsmall;
     }
     if (nsmall > 0) {

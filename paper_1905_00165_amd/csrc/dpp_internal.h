@@ -178,11 +178,11 @@ hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* 
                                int64_t j0, int ss, hipStream_t s);
 
 // Small Hermitian real problems (n <= kSmallMax, FP64 or FP32 storage), one
-// workgroup each with the whole lower triangle in LDS (small_ldlh.hip): the
-// decisions, the factor or conditional kernel in A, mask and pivots; loglik
-// and info come from launch_finalize as for the other problems.
+// workgroup each with the whole lower triangle in FP64 registers
+// (small_ldlh.hip): the decisions, the factor or conditional kernel in A,
+// mask and pivots; loglik and info come from launch_finalize as for the other
+// problems.
 constexpr int64_t kSmallMax = 192;
-size_t small_ldlh_lds_bytes(int64_t n);
 hipError_t launch_small_ldlh(int dtype, const DevProb* probs, int nprob, int64_t nmax,
                              hipStream_t s);
 

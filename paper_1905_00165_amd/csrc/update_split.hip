@@ -440,7 +440,9 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     const int nstages = kwp / S::KC;
     for (int p = 0; p < S::NST - 1; ++p)
         if (p < nstages) issue_stage(p * S::KC, p);
-    for (int st = 0; st < nstages; ++st) {
+    // One stage: wait for its copies, refill the buffer freed last, then its
+    // k steps on the matrix cores.
+    auto stage = [&](int st) {
         const int buf = st % S::NST;
         // This wavefront's copies of stage st are in LDS (the later stages
         // already issued may still be in flight); the barrier makes everyone's
@@ -523,21 +525,29 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
             }
             __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - rest, 0);
         }
-        if constexpr (ACC64) {
-            // Every FL stages (and after the last) the FP32 sums move into
-            // the FP64 accumulators and restart from zero.
-            if ((st + 1) % S::FL == 0 || st == nstages - 1) {
+    };
+    if constexpr (ACC64) {
+        // Chunks of FL stages; after each the FP32 sums move into the FP64
+        // accumulators and restart from zero. The flush sits outside the
+        // stage loop, unconditionally: a flush inside it (taken on some
+        // iterations) makes the accumulators a merge of two values at the
+        // loop's back edge, which the compiler then keeps in VGPRs and copies
+        // to and from the MFMA's accumulation registers every stage.
+        for (int s0 = 0; s0 < nstages; s0 += S::FL) {
+            const int s1 = s0 + S::FL < nstages ? s0 + S::FL : nstages;
+            for (int st = s0; st < s1; ++st) stage(st);
 #pragma unroll
-                for (int rb = 0; rb < S::RB; ++rb)
+            for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
-                    for (int cb = 0; cb < S::CB; ++cb)
+                for (int cb = 0; cb < S::CB; ++cb)
 #pragma unroll
-                        for (int e = 0; e < 16; ++e) {
-                            acc64[rb][cb][e] += (double)acc[rb][cb][e];
-                            acc[rb][cb][e] = 0.0f;
-                        }
-            }
+                    for (int e = 0; e < 16; ++e) {
+                        acc64[rb][cb][e] += (double)acc[rb][cb][e];
+                        acc[rb][cb][e] = 0.0f;
+                    }
         }
+    } else {
+        for (int st = 0; st < nstages; ++st) stage(st);
     }
 
     // Accumulator layout of the 32x32 MFMA with the column operand first:
