@@ -151,23 +151,6 @@ constexpr int vmcnt_imm()
 static_assert(vmcnt_imm<0>() == 0x0F70 && vmcnt_imm<6>() == 0x0F76 && vmcnt_imm<24>() == 0x4F78,
               "s_waitcnt encoding");
 
-// Wait until at most (stages still in flight) * PER_WAVE loads are
-// outstanding; `later` is 0 .. NST - 2, the stages issued after this one.
-template <int NST, int PER_WAVE>
-__device__ __forceinline__ void wait_stages_le(int later)
-{
-    static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
-    if (NST >= 4 && later == 2) {
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NST >= 4 ? 2 : 0) * PER_WAVE>());
-        return;
-    }
-    if (NST >= 3 && later == 1) {
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm<(NST >= 3 ? 1 : 0) * PER_WAVE>());
-        return;
-    }
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
-}
-
 constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format, gfx9 resource word 3
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -295,32 +278,44 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     // of the buffer (the pieces of L, then of W, back to back): 1024 / ROWB rows of
     // one plane. Lane l supplies row l / LPR of that block, physical segment
     // l % LPR, i.e. logical segment (l % LPR) ^ swz(row); the block starts at a
-    // multiple of 16 rows, so swz depends on l only.
+    // multiple of 16 rows, so swz depends on l only. A lane's source for a
+    // stage at k offset kc is its pointer at kc = 0 plus kc * 32 elements:
+    // plane_off is linear in k across steps of 16 (512 elements per step, the
+    // rows' 32-k blocks being consecutive), so the pointers are formed once.
     const int rl = lane / S::LPR;
     const int seg8 = ((lane % S::LPR) ^ swz<S::ROWB>(rl)) * 8;
-    auto issue_stage = [&](int kc, int buf) {
+    const uint16_t* src[S::PER_WAVE];
 #pragma unroll
-        for (int q = 0; q < S::PER_WAVE; ++q) {
-            const int i = wave * S::PER_WAVE + q;  // copy index, uniform
-            const int off = i * 1024;
-            int plane, row0;
-            if (off < S::NP * S::A_PLANE) {
-                plane = off / S::A_PLANE;
-                row0 = (off % S::A_PLANE) / S::ROWB;
-            } else {
-                const int o2 = off - S::NP * S::A_PLANE;
-                plane = S::NP + o2 / S::W_PLANE;
-                row0 = (o2 % S::W_PLANE) / S::ROWB;
-            }
-            const int64_t first = plane < S::NP ? rowT0 : colT0;
-            const int64_t last = (plane < S::NP ? rEnd : colEnd) - 1;  // rows past it: reuse it
-            int64_t g = first + row0 + rl;
-            g = g < last ? g : last;
-            __builtin_amdgcn_global_load_lds(
-                (gptr_t)(split_plane(P.split, RS * n, n, ss, S::NP, plane) +
-                         plane_off(g, kk0 + kc + seg8, ss)),
-                (lptr_t)(lds + buf * S::BUF + off), 16, 0, 0);
+    for (int q = 0; q < S::PER_WAVE; ++q) {
+        const int i = wave * S::PER_WAVE + q;  // copy index, uniform
+        const int off = i * 1024;
+        int plane, row0;
+        if (off < S::NP * S::A_PLANE) {
+            plane = off / S::A_PLANE;
+            row0 = (off % S::A_PLANE) / S::ROWB;
+        } else {
+            const int o2 = off - S::NP * S::A_PLANE;
+            plane = S::NP + o2 / S::W_PLANE;
+            row0 = (o2 % S::W_PLANE) / S::ROWB;
         }
+        const int64_t first = plane < S::NP ? rowT0 : colT0;
+        const int64_t last = (plane < S::NP ? rEnd : colEnd) - 1;  // rows past it: reuse it
+        int64_t g = first + row0 + rl;
+        g = g < last ? g : last;
+        src[q] = split_plane(P.split, RS * n, n, ss, S::NP, plane) + plane_off(g, kk0 + seg8, ss);
+    }
+    const int nstages = kwp / S::KC;
+    // Every stage issues its copies, also past the last one (they then reread
+    // the last stage into the buffer freed next), so that the copies are
+    // branch-free and can be interleaved with the matrix products, and the
+    // wait below has one form. They are drained before the epilogue.
+    auto issue_stage = [&](int st) {
+        const int64_t kc = (int64_t)(st < nstages ? st : nstages - 1) * S::KC;
+        unsigned char* const dst = lds + (st % S::NST) * S::BUF + wave * S::PER_WAVE * 1024;
+#pragma unroll
+        for (int q = 0; q < S::PER_WAVE; ++q)
+            __builtin_amdgcn_global_load_lds((gptr_t)(src[q] + kc * 32), (lptr_t)(dst + q * 1024), 16, 0,
+                                             0);
     };
 
     f16v acc[S::RB][S::CB];
@@ -437,18 +432,16 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     };
 
     double cva[CP][16], cvb[CP][16];
-    const int nstages = kwp / S::KC;
-    for (int p = 0; p < S::NST - 1; ++p)
-        if (p < nstages) issue_stage(p * S::KC, p);
+    for (int p = 0; p < S::NST - 1; ++p) issue_stage(p);
     // One stage: wait for its copies, refill the buffer freed last, then its
     // k steps on the matrix cores.
-    auto stage = [&](int st) {
+    auto stage = [&](int st, bool prefetch_c) {
         const int buf = st % S::NST;
-        // This wavefront's copies of stage st are in LDS (the later stages
-        // already issued may still be in flight); the barrier makes everyone's
-        // visible and retires every read of the buffer refilled next.
-        const int later = nstages - 1 - st < S::NST - 2 ? nstages - 1 - st : S::NST - 2;
-        wait_stages_le<S::NST, S::PER_WAVE>(later);
+        // This wavefront's copies of stage st are in LDS (the NST - 2 later
+        // stages already issued may still be in flight); the barrier makes
+        // everyone's visible and retires every read of the buffer refilled
+        // next.
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm<(S::NST - 2) * S::PER_WAVE>());
         // A bare s_barrier: __syncthreads() would add a release fence, i.e.
         // vmcnt(0), and drain the stages still in flight. Ordering needs no
         // fence here: each wavefront has waited for its own copies of this
@@ -456,10 +449,9 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         // the MFMAs that consumed them. The memory clobber keeps the compiler
         // from moving LDS accesses across the barrier.
         asm volatile("s_barrier" ::: "memory");
-        if (st + S::NST - 1 < nstages) issue_stage((st + S::NST - 1) * S::KC, (st + S::NST - 1) % S::NST);
         // First C round in flight during the last stage (with three pieces
         // the fragments leave no registers for it: loaded after the loop).
-        else if (S::NP == 2 && st == nstages - 1) c_load(0, cva);
+        if (S::NP == 2 && prefetch_c) c_load(0, cva);
         const unsigned char* B0 = lds + buf * S::BUF;
         bf8 lp[S::NP][S::KSTEPS][S::RB], wp[S::NP][S::KSTEPS][S::CB];
         auto read_l = [&](int p, int ks) {
@@ -505,25 +497,42 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         if constexpr (S::KSTEPS == 2) {
             read_frags(0);
             read_frags(1);
+            // The next stage's copies after this stage's fragment reads (they
+            // write LDS, so they cannot move above reads of LDS; the buffer
+            // they fill was last read before the barrier).
+            issue_stage(st + S::NST - 1);
             mfmas(0);
             mfmas(1);
             // Schedule: k step 0's fragment reads, then its MFMAs with k step
-            // 1's reads interleaved evenly, then k step 1's MFMAs.
+            // 1's reads interleaved evenly, then k step 1's MFMAs with the
+            // next stage's copies in between.
+            static_assert(S::MFMAS >= S::PER_WAVE, "a product per copy");
             __builtin_amdgcn_sched_group_barrier(0x100, S::READS, 0);  // DS read
             interleave_mfma_reads<S::MFMAS, S::READS>();
-            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS, 0);
+            for (int q = 0; q < S::PER_WAVE; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - S::PER_WAVE, 0);
         } else {
             read_frags(0);
+            issue_stage(st + S::NST - 1);  // after the fragment reads, as above
             mfmas(0);
             // Schedule: the fragments of the first product term (p0 x p0'),
-            // then its MFMAs with the remaining fragment reads interleaved.
+            // then its MFMAs with the remaining fragment reads interleaved,
+            // then the next stage's copies between further MFMAs.
             constexpr int first = S::RB + S::CB, rest = S::READS - first;
+            static_assert(S::MFMAS - rest >= S::PER_WAVE, "a product per copy");
             __builtin_amdgcn_sched_group_barrier(0x100, first, 0);
             for (int r = 0; r < rest; ++r) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             }
-            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - rest, 0);
+            for (int q = 0; q < S::PER_WAVE; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - rest - S::PER_WAVE, 0);
         }
     };
     if constexpr (ACC64) {
@@ -535,7 +544,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         // to and from the MFMA's accumulation registers every stage.
         for (int s0 = 0; s0 < nstages; s0 += S::FL) {
             const int s1 = s0 + S::FL < nstages ? s0 + S::FL : nstages;
-            for (int st = s0; st < s1; ++st) stage(st);
+            for (int st = s0; st < s1; ++st) stage(st, false);
 #pragma unroll
             for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
@@ -547,8 +556,13 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
                     }
         }
     } else {
-        for (int st = 0; st < nstages; ++st) stage(st);
+        // The last stage apart: it also starts the first C round's loads.
+        for (int st = 0; st < nstages - 1; ++st) stage(st, false);
+        stage(nstages - 1, true);
     }
+    // The copies issued past the last stage still write LDS: drain them
+    // before the workgroup can end.
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
 
     // Accumulator layout of the 32x32 MFMA with the column operand first:
     // element e of lane l is C row (l % 32), C column 8*(e/4) + 4*(l/32) + e%4
