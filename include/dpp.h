@@ -77,8 +77,9 @@ typedef enum { DPP_F64 = 0, DPP_F32 = 1, DPP_C128 = 2 } dpp_dtype;
    p2 = bf16(x - p0 - p1) and the six products p0*p0' + p0*p1' + p1*p0' +
    p0*p2' + p2*p0' + p1*p1' on BF16 MFMA (about 2^-24 of each product is
    lost), at twice the matrix-core work of DPP_PREC_SPLIT_BF16; the FP32
-   accumulation runs over at most 64 values of k, whose sums are accumulated
-   in FP64, so the rounding of long FP32 sums does not enter.
+   sum is two-level: the matrix cores accumulate 64 values of k at a time,
+   and those chunk sums are added up in FP32, so no FP32 sum runs over more
+   than max(64, k / 64) terms.
    Every form subtracts the sum from the stored value in the storage
    precision. The diagonal-block decisions, the panel solves and the
    log-likelihood stay in FP64 on every path. */

@@ -8,12 +8,13 @@
 //   NP = 2 (update_bf16x3): hi*hi' + hi*lo' + lo*hi'; the dropped lo*lo' and
 //     the pieces' rounding leave about 2^-16 of each product;
 //   NP = 3 (update_bf16x6): p0*p0' + p0*p1' + p1*p0' + p0*p2' + p2*p0' +
-//     p1*p1'; about 2^-24 of each product is left. FP32 sums over long k
-//     ranges would then dominate the error (each addition rounds to 2^-24 of
-//     a partial sum that can be much larger than the result), so the FP32
-//     accumulators are added into FP64 ones every 64 k (Shape::FL) and
-//     restart from zero: 64 x 64 per wavefront, one wavefront per SIMD, so
-//     that both sets fit the registers.
+//     p1*p1'; about 2^-24 of each product is left. One FP32 sum over a long
+//     k range would then dominate the error (each addition rounds to 2^-24
+//     of a partial sum that can be much larger than the result), so the sum
+//     is two-level: the MFMAs accumulate 64 k at a time (Shape::FL) from
+//     zero, and each such chunk sum is added into a second FP32 total, so no
+//     FP32 sum runs over more than max(64, kw / 64) terms. Both sets fit two
+//     wavefronts per SIMD (64 x 64 per wavefront).
 // The sum is subtracted from the stored value in FP64 and rounded to the
 // storage type.
 //
@@ -63,9 +64,9 @@ constexpr int kGroupCols = 4;      // tile columns per group of the wide order
 
 // TM x TN tile on WR x WC wavefronts; K advances KC at a time through NST LDS
 // stages (NST - 1 of them in flight while one is multiplied); NP BF16 pieces
-// per operand value. FL > 0: the FP32 accumulators are added into FP64 ones
-// (and restart from zero) every FL stages, so no FP32 sum runs over more than
-// FL * KC values of k.
+// per operand value. FL > 0: the FP32 accumulators are added into FP32
+// totals (and restart from zero) every FL stages, so no MFMA chain runs over
+// more than FL * KC values of k.
 template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_, int KC_, int NST_, int NP_,
           int FL_ = 0>
 struct Shape {
@@ -74,7 +75,7 @@ struct Shape {
     static constexpr int EP = EP_;      // 32x32 blocks per epilogue round
     static constexpr int KC = KC_, NST = NST_;
     static constexpr int NP = NP_;                                 // pieces per value
-    static constexpr int FL = FL_;                                 // stages per FP64 flush (0: none)
+    static constexpr int FL = FL_;                                 // stages per chunk (0: one chain)
     static constexpr int NTERM = NP == 2 ? 3 : 6;                  // product terms
     static constexpr int ROWB = KC * 2;                            // bytes per operand row and stage
     static constexpr int KSTEPS = KC / 16;                         // MFMA k steps per stage
@@ -103,11 +104,11 @@ __device__ __forceinline__ constexpr int term_b(int t) { return t == 1 ? 1 : t =
 using Wide3 = Shape<256, 256, 2, 4, 1, 1, 16, 4, 2>;
 using Medium3 = Shape<256, 128, 2, 2, 2, 1, 16, 3, 2>;
 using Narrow3 = Shape<128, 64, 4, 1, 3, 1, 32, 2, 2>;
-// Six products: FP32 sums over 64 k at most, accumulated in FP64 (64 x 64
-// per wavefront, so the FP64 accumulators fit beside the FP32 ones).
-using Wide6 = Shape<128, 128, 2, 2, 1, 1, 16, 4, 3, 4>;
+// Six products: MFMA chains of 64 k, summed into FP32 totals (64 x 64 per
+// wavefront, so both sets fit two workgroups per CU; three LDS stages).
+using Wide6 = Shape<128, 128, 2, 2, 2, 1, 16, 3, 3, 4>;
 using Medium6 = Wide6;
-using Narrow6 = Shape<128, 64, 4, 1, 1, 1, 32, 2, 3, 2>;
+using Narrow6 = Shape<128, 64, 4, 1, 2, 1, 32, 2, 3, 2>;
 
 // MFMAs spread evenly over the READS fragment reads that follow the first
 // group: slot r gets floor((r+1) M / R) - floor(r M / R) MFMAs, then one read.
@@ -325,19 +326,19 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         for (int cb = 0; cb < S::CB; ++cb)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.0f;
-    constexpr bool ACC64 = S::FL > 0;
-    double acc64[ACC64 ? S::RB : 1][ACC64 ? S::CB : 1][16];
-    if constexpr (ACC64) {
+    constexpr bool TWO_LEVEL = S::FL > 0;  // two-level sums (chunks, then FP32 totals)
+    float acct[TWO_LEVEL ? S::RB : 1][TWO_LEVEL ? S::CB : 1][16];
+    if constexpr (TWO_LEVEL) {
 #pragma unroll
         for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < S::CB; ++cb)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) acc64[rb][cb][e] = 0.0;
+                for (int e = 0; e < 16; ++e) acct[rb][cb][e] = 0.0f;
     }
     // The value of the update at accumulator element e of block (rb, cb).
     auto acc_value = [&](int rb, int cb, int e) -> double {
-        if constexpr (ACC64) return acc64[rb][cb][e];
+        if constexpr (TWO_LEVEL) return (double)acct[rb][cb][e];
         return (double)acc[rb][cb][e];
     };
 
@@ -535,9 +536,9 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
             __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - rest - S::PER_WAVE, 0);
         }
     };
-    if constexpr (ACC64) {
-        // Chunks of FL stages; after each the FP32 sums move into the FP64
-        // accumulators and restart from zero. The flush sits outside the
+    if constexpr (TWO_LEVEL) {
+        // Chunks of FL stages; after each the FP32 sums move into the FP32
+        // totals and restart from zero. The flush sits outside the
         // stage loop, unconditionally: a flush inside it (taken on some
         // iterations) makes the accumulators a merge of two values at the
         // loop's back edge, which the compiler then keeps in VGPRs and copies
@@ -551,7 +552,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
                 for (int cb = 0; cb < S::CB; ++cb)
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
-                        acc64[rb][cb][e] += (double)acc[rb][cb][e];
+                        acct[rb][cb][e] += acc[rb][cb][e];
                         acc[rb][cb][e] = 0.0f;
                     }
         }
