@@ -529,6 +529,12 @@ def bench_lensemble(torch, B, W, dev, count=4096):
         # The same call launched eagerly: host work (the binding's marshalling
         # of 4096 problem descriptors, then the enqueue) sets the pace here.
         ms_eager = eager_time(torch, step, reps=3)
+        # Where the device time goes: the library's own event profile of one
+        # eager call (launches and milliseconds per kernel family).
+        B.dpp_profile_begin()
+        step()
+        torch.cuda.synchronize()
+        prof = B.dpp_profile_end()
         sizes = np.array([int(x) for x in torch.stack([o["mask"].sum() for o in outs]).cpu()])
         out[name] = {"ms_per_call": round(ms, 3), "samples_per_s": round(count / (ms * 1e-3), 1),
                      "frac_of_hbm_floor": round(compulsory / PEAK_HBM * 1e3 / ms, 4),
@@ -536,7 +542,9 @@ def bench_lensemble(torch, B, W, dev, count=4096):
                      "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
                      "info_all_zero": bool((infos == 0).all().item()),
                      "max_size": int(sizes.max()), "size_le_rank": bool((sizes <= 64).all()),
-                     "workspace_gb": round(ws.numel() / 1e9, 2)}
+                     "workspace_gb": round(ws.numel() / 1e9, 2),
+                     "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
+                                 for k, v in prof.items()}}
         del ws
         torch.cuda.empty_cache()
 

@@ -84,14 +84,15 @@ struct Shape {
     static constexpr int A_PLANE = TM * ROWB, W_PLANE = TN * ROWB;
     static constexpr int BUF = NP * (A_PLANE + W_PLANE);           // pieces of L, then of W
     static constexpr int LDS = NST * BUF;
-    static constexpr int PER_WAVE = BUF / 1024 / NW;                // 1 KiB copies per stage
+    static constexpr int COPIES = BUF / 1024;                       // 1 KiB copies per stage
+    static constexpr int PER_WAVE = (COPIES + NW - 1) / NW;         // per wavefront
     static constexpr int LPR = ROWB / 16;                           // lanes per row in a copy
     static constexpr int READS = NP * (RB + CB);                    // fragments per k step
     static constexpr int MFMAS = NTERM * RB * CB;
     static_assert(NP == 2 || NP == 3, "two or three pieces");
     static_assert(KC == 16 || KC == 32, "rows of 32 or 64 bytes");
     static_assert(kKAlign % KC == 0, "stages must tile every k range");
-    static_assert(BUF % (1024 * NW) == 0, "copies must split evenly over wavefronts");
+    static_assert(BUF % 1024 == 0, "whole 1 KiB copies");
     static_assert(A_PLANE % 1024 == 0 && W_PLANE % 1024 == 0, "no copy straddles two planes");
     static_assert(LDS <= 160 * 1024 / MINB, "LDS of MINB workgroups per CU");
     static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
@@ -266,7 +267,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar arithmetic
     const int wr = wave / S::WC, wc = wave % S::WC;
 
     const int64_t rowT0 = rg.r0 * RS + tc.i0 * S::TM;  // real rows of C'
@@ -286,9 +287,15 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     const int rl = lane / S::LPR;
     const int seg8 = ((lane % S::LPR) ^ swz<S::ROWB>(rl)) * 8;
     const uint16_t* src[S::PER_WAVE];
+    int dst_off[S::PER_WAVE];  // byte offset of each copy in a stage buffer
 #pragma unroll
     for (int q = 0; q < S::PER_WAVE; ++q) {
-        const int i = wave * S::PER_WAVE + q;  // copy index, uniform
+        // Copy index, uniform. When the wavefronts do not divide the copies
+        // evenly, the last one repeats the last copy (the same bytes to the
+        // same place), so every wavefront issues PER_WAVE and stays
+        // branch-free.
+        int i = wave * S::PER_WAVE + q;
+        i = i < S::COPIES ? i : S::COPIES - 1;
         const int off = i * 1024;
         int plane, row0;
         if (off < S::NP * S::A_PLANE) {
@@ -304,6 +311,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         int64_t g = first + row0 + rl;
         g = g < last ? g : last;
         src[q] = split_plane(P.split, RS * n, n, ss, S::NP, plane) + plane_off(g, kk0 + seg8, ss);
+        dst_off[q] = off;
     }
     const int nstages = kwp / S::KC;
     // Every stage issues its copies, also past the last one (they then reread
@@ -312,10 +320,10 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     // wait below has one form. They are drained before the epilogue.
     auto issue_stage = [&](int st) {
         const int64_t kc = (int64_t)(st < nstages ? st : nstages - 1) * S::KC;
-        unsigned char* const dst = lds + (st % S::NST) * S::BUF + wave * S::PER_WAVE * 1024;
+        unsigned char* const dst = lds + (st % S::NST) * S::BUF;
 #pragma unroll
         for (int q = 0; q < S::PER_WAVE; ++q)
-            __builtin_amdgcn_global_load_lds((gptr_t)(src[q] + kc * 32), (lptr_t)(dst + q * 1024), 16, 0,
+            __builtin_amdgcn_global_load_lds((gptr_t)(src[q] + kc * 32), (lptr_t)(dst + dst_off[q]), 16, 0,
                                              0);
     };
 
