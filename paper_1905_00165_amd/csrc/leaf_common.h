@@ -29,7 +29,21 @@ constexpr int L = kLeaf;
 // (or columns); a staged 16 x 64 tile per wavefront.
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * 64;
-constexpr int kTilePitch = 66;  // doubles per row of a staged 16 x 64 tile
+// LDS pitches (in doubles), chosen so that a wavefront's FP64 accesses spread
+// over the 64 four-byte banks (32 doubles wide) as evenly as 64 lanes allow,
+// two per double-wide bank, or three where two patterns share a layout:
+//   a factored 64 x 64 block, read by solve_group as Tt[(16c + 4s + q) * kBP
+//     + 16b + i16]: lane (q, i16) at q * kBP + i16, two-way for kBP = 72;
+//   the inverses of its 16 x 16 diagonal blocks, read as Inv[i16 * kInvPitch
+//     + 4s + q]: two-way for kInvPitch = 18;
+//   a staged 16 x 64 tile, written at i16 * kTilePitch + q (three-way) and
+//     read at tr * kTilePitch + 8 m (two-way) for kTilePitch = 67.
+constexpr int kBP = 72;
+constexpr int kInvPitch = 18;
+constexpr int kInvBlock = 16 * kInvPitch;  // doubles per inverse block; four per block
+constexpr int kTilePitch = 67;
+// Two workgroups per CU need at most half of the 160 KiB of LDS each.
+constexpr int kLdsPerTwo = 80 * 1024;
 
 // Every workgroup of a diagonal-block launch first runs the 64-step chain,
 // then its share of the panel, one group of 16 rows after the other on each
@@ -232,8 +246,9 @@ __device__ __forceinline__ int tidx(int t, int k)
 // One group of 16 rows. Lane (q, i16) = (lane / 16, lane % 16) holds in
 // cur[4b + e] row i16, column 16b + 4e + q of A and receives the same entry
 // of X in x[b][e]. T[k][t] is Tt[tidx<LD, TR>(t, k)]; only the blocks below
-// the diagonal blocks are read. Inv[b * 256 + i * 16 + k] = (T_bb^{-1})[i][k].
-template <int LD = L, bool TR = false>
+// the diagonal blocks are read. Inv[b * kInvBlock + i * kInvPitch + k] =
+// (T_bb^{-1})[i][k].
+template <int LD = kBP, bool TR = false>
 __device__ __forceinline__ void solve_group(const double* Tt, const double* Inv,
                                             const double (&cur)[16], d4 (&x)[4], int q, int i16)
 {
@@ -247,7 +262,7 @@ __device__ __forceinline__ void solve_group(const double* Tt, const double* Inv,
                 acc = mfma16(-Tt[tidx<LD, TR>(16 * c + 4 * s + q, 16 * b + i16)], x[c][s], acc);
         d4 xb = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) xb = mfma16(Inv[b * 256 + i16 * 16 + 4 * s + q], acc[s], xb);
+        for (int s = 0; s < 4; ++s) xb = mfma16(Inv[b * kInvBlock + i16 * kInvPitch + 4 * s + q], acc[s], xb);
         x[b] = xb;
     }
 }
@@ -255,7 +270,7 @@ __device__ __forceinline__ void solve_group(const double* Tt, const double* Inv,
 // Inverses of the four 16x16 diagonal blocks of T (lower triangular, unit
 // diagonal if UNIT; T[k][t] = Tt[tidx<LD, TR>(t, k)] as for solve_group) by
 // forward substitution, one column per lane of the calling wavefront.
-template <bool UNIT, int LD = L, bool TR = false>
+template <bool UNIT, int LD = kBP, bool TR = false>
 __device__ __forceinline__ void invert_diag_blocks(const double* Tt, double* Inv, int lane)
 {
     const int b = lane >> 4, c = lane & 15;
@@ -268,7 +283,7 @@ __device__ __forceinline__ void invert_diag_blocks(const double* Tt, double* Inv
         y[k] = UNIT ? acc : acc / Tt[tidx<LD, TR>(16 * b + k, 16 * b + k)];
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) Inv[b * 256 + k * 16 + c] = y[k];
+    for (int k = 0; k < 16; ++k) Inv[b * kInvBlock + k * kInvPitch + c] = y[k];
 }
 
 }  // namespace leaf

@@ -51,7 +51,7 @@ __device__ __forceinline__ cd buf_load_c(__amdgpu_buffer_rsrc_t r, int voff, int
             __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff + 8, soff, 0))};
 }
 
-// Tt[t' * 64 + k'] = T[k'][t'] for the real form T = R(T_c) of a complex lower
+// Tt[t' * kBP + k'] = T[k'][t'] for the real form T = R(T_c) of a complex lower
 // triangular 32 x 32 matrix T_c: lane k (< 32) holds row k of T_c in z[0..31]
 // (z[t] = T_c[k][t] for t <= k) and writes real columns 2k, 2k + 1 of every
 // real row pair; entries above the complex diagonal are written as zeros.
@@ -62,10 +62,10 @@ __device__ __forceinline__ void store_real_form(double* Tt, const cd (&z)[LC], i
     for (int t = 0; t < LC; ++t) {
         const cd v = t <= k ? z[t] : cd{0.0, 0.0};
         // R(v) = [[Re, -Im], [Im, Re]] at rows 2k + s', columns 2t + s.
-        Tt[(2 * t) * LR + 2 * k] = v.x;
-        Tt[(2 * t) * LR + 2 * k + 1] = v.y;
-        Tt[(2 * t + 1) * LR + 2 * k] = -v.y;
-        Tt[(2 * t + 1) * LR + 2 * k + 1] = v.x;
+        Tt[(2 * t) * kBP + 2 * k] = v.x;
+        Tt[(2 * t) * kBP + 2 * k + 1] = v.y;
+        Tt[(2 * t + 1) * kBP + 2 * k] = -v.y;
+        Tt[(2 * t + 1) * kBP + 2 * k + 1] = v.x;
     }
 }
 
@@ -112,12 +112,14 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_zldlh(const DevProb* __restr
     int64_t lds;
     const cd* __restrict__ S = first_source<cd>(P, c0 == 0, lds);
 
-    __shared__ __attribute__((aligned(16))) double smem[2 * LC + LC + LR * LR + 4 * 16 * 16 + kWaves * 16 * kTilePitch];
+    constexpr int kSmem = 2 * LC + LC + LR * kBP + 4 * kInvBlock + kWaves * 16 * kTilePitch;
+    static_assert(kSmem * sizeof(double) <= kLdsPerTwo, "two workgroups per CU");
+    __shared__ __attribute__((aligned(16))) double smem[kSmem];
     cd* const sB = reinterpret_cast<cd*>(smem);  // chain: the unscaled column of the pivot
     double* const sR = smem + 2 * LC;            // 1 / D1
     double* const sL = sR + LC;                  // real form of T_c = conj(L11), as Tt
-    double* const sI = sL + LR * LR;             // inverses of its 16 x 16 diagonal blocks
-    double* const sT = sI + 4 * 16 * 16;         // per wavefront: one row group, row-major
+    double* const sI = sL + LR * kBP;            // inverses of its 16 x 16 diagonal blocks
+    double* const sT = sI + 4 * kInvBlock;       // per wavefront: one row group, row-major
 
     const int tid = threadIdx.x;
     if (tid < 64) {
@@ -180,10 +182,10 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_zldlh(const DevProb* __restr
             for (int t = 0; t < LC; ++t) {
                 const cd v = (t < lane && lane < bs) ? cd{a[t].x, -a[t].y}
                                                      : (t == lane ? cd{1.0, 0.0} : cd{0.0, 0.0});
-                sL[(2 * t) * LR + 2 * lane] = v.x;
-                sL[(2 * t) * LR + 2 * lane + 1] = v.y;
-                sL[(2 * t + 1) * LR + 2 * lane] = -v.y;
-                sL[(2 * t + 1) * LR + 2 * lane + 1] = v.x;
+                sL[(2 * t) * kBP + 2 * lane] = v.x;
+                sL[(2 * t) * kBP + 2 * lane + 1] = v.y;
+                sL[(2 * t + 1) * kBP + 2 * lane] = -v.y;
+                sL[(2 * t + 1) * kBP + 2 * lane + 1] = v.x;
             }
             sR[lane] = lane < bs ? 1.0 / mydp : 1.0;
             if (bx == 0 && lane < bs) {
@@ -310,11 +312,11 @@ __global__ __launch_bounds__(kThreads, 1) void leaf_zlu(const DevProb* __restric
     int64_t lds;
     const cd* __restrict__ S = first_source<cd>(P, c0 == 0, lds);
 
-    __shared__ __attribute__((aligned(16))) double smem[kWaves * 16 * kTilePitch + LR * LR + 4 * 16 * 16 + 2 * LC * LC];
+    __shared__ __attribute__((aligned(16))) double smem[kWaves * 16 * kTilePitch + LR * kBP + 4 * kInvBlock + 2 * LC * LC];
     double* const sT = smem;
     double* const sP = smem + kWaves * 16 * kTilePitch;  // real form of the current T_c, as Tt
-    double* const sI = sP + LR * LR;                     // inverses of its diagonal blocks
-    cd* const sC = reinterpret_cast<cd*>(sI + 4 * 16 * 16);  // the factored block, by columns
+    double* const sI = sP + LR * kBP;                    // inverses of its diagonal blocks
+    cd* const sC = reinterpret_cast<cd*>(sI + 4 * kInvBlock);  // the factored block, by columns
 
     const int tid = threadIdx.x;
     if (tid < 64) {
@@ -403,7 +405,8 @@ __global__ __launch_bounds__(kThreads, 1) void leaf_zlu(const DevProb* __restric
         // Inverses of R(T_c)'s 16 x 16 diagonal blocks: forward substitution
         // on T_c's 8 x 8 diagonal blocks in complex arithmetic, one column per
         // lane (block lane / 8, column lane % 8), T_c[k][t] = sC[k * LC + t];
-        // then sI[b * 256 + i * 16 + c] = R((T_c,bb)^{-1}) (R carries inverses).
+        // then sI[b * kInvBlock + i * kInvPitch + c] = R((T_c,bb)^{-1}) (R
+        // carries inverses).
         const int lane = tid;
         if (lane < LC) {
             const int b = lane >> 3, c = lane & 7;
@@ -423,10 +426,10 @@ __global__ __launch_bounds__(kThreads, 1) void leaf_zlu(const DevProb* __restric
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                sI[b * 256 + (2 * k) * 16 + 2 * c] = y[k].x;
-                sI[b * 256 + (2 * k) * 16 + 2 * c + 1] = -y[k].y;
-                sI[b * 256 + (2 * k + 1) * 16 + 2 * c] = y[k].y;
-                sI[b * 256 + (2 * k + 1) * 16 + 2 * c + 1] = y[k].x;
+                sI[b * kInvBlock + (2 * k) * kInvPitch + 2 * c] = y[k].x;
+                sI[b * kInvBlock + (2 * k) * kInvPitch + 2 * c + 1] = -y[k].y;
+                sI[b * kInvBlock + (2 * k + 1) * kInvPitch + 2 * c] = y[k].y;
+                sI[b * kInvBlock + (2 * k + 1) * kInvPitch + 2 * c + 1] = y[k].x;
             }
         }
     }

@@ -46,12 +46,14 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
     // One LDS array carved by hand so that sB sits at address 0: the chain's
     // 64-entry broadcast reads then all use one base register and immediate
     // offsets.
-    __shared__ __attribute__((aligned(16))) double smem[2 * L + L * L + 4 * 16 * 16 + kWaves * 16 * kTilePitch];
+    constexpr int kSmem = 2 * L + L * kBP + 4 * kInvBlock + kWaves * 16 * kTilePitch;
+    static_assert(kSmem * sizeof(double) <= kLdsPerTwo, "two workgroups per CU");
+    __shared__ __attribute__((aligned(16))) double smem[kSmem];
     double* const sB = smem;               // chain: broadcast columns of the current two pivots
     double* const sR = smem + L;           // 1 / D1 (written after the chain, over sB's second half)
-    double* const sL = smem + 2 * L;       // sL[t*L + k] = L11[k][t] for k > t, zero elsewhere
-    double* const sI = sL + L * L;         // sI[b*256 + i*16 + k] = (L_bb^{-1})[i][k]
-    double* const sT = sI + 4 * 16 * 16;   // per wavefront: W of one row group, row-major
+    double* const sL = smem + 2 * L;       // sL[t*kBP + k] = L11[k][t] for k > t, zero elsewhere
+    double* const sI = sL + L * kBP;       // the inverses of L11's 16 x 16 diagonal blocks
+    double* const sT = sI + 4 * kInvBlock;  // per wavefront: W of one row group, row-major
 
     const int tid = threadIdx.x;
     if (tid < L) {
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
         }
 
 #pragma unroll
-        for (int k = 0; k < L; ++k) sL[k * L + lane] = (k < lane && lane < bs) ? a[k] : 0.0;
+        for (int k = 0; k < L; ++k) sL[k * kBP + lane] = (k < lane && lane < bs) ? a[k] : 0.0;
         sR[lane] = (lane < bs) ? 1.0 / mydp : 1.0;
 
         // The factored block goes to the workspace strip, not to A: other

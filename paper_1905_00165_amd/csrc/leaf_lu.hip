@@ -34,7 +34,7 @@ using namespace leaf;
 // set of diagonal-block inverses, those of U11^T for the column panel, then
 // those of L11 for the row panel: 75 KiB, so two workgroups fit on a CU when
 // a launch needs more than one round.
-constexpr int kLP = L + 1;
+constexpr int kLP = 70;  // three-way at worst for both read orders of solve_group
 
 template <typename T, int NPC>
 __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict__ probs, GroupMap M,
@@ -56,7 +56,9 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_lu(const DevProb* __restrict
 
     // sP[k + t*kLP] = entry (k, t) of the factored block: L11[k][t] for k > t,
     // U11[k][t] for k <= t.
-    __shared__ double smem[kWaves * 16 * kTilePitch + L * kLP + 4 * 16 * 16];
+    constexpr int kSmem = kWaves * 16 * kTilePitch + L * kLP + 4 * kInvBlock;
+    static_assert(kSmem * sizeof(double) <= kLdsPerTwo, "two workgroups per CU");
+    __shared__ double smem[kSmem];
     double* const sT = smem;
     double* const sP = smem + kWaves * 16 * kTilePitch;
     double* const sI = sP + L * kLP;                 // inverses of the diagonal blocks
