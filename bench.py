@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--batch", type=int, default=64, help="samples per batched call")
     p.add_argument("--calls", type=int, default=1,
                    help="batched calls per step (each on its own streams of uniforms)")
-    p.add_argument("--prec", choices=["all", "split6", "split", "fp64"], default="all")
+    p.add_argument("--prec", choices=["all", "split6", "fp16", "split", "fp64"], default="all")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the oracle baselines of the extra workloads; "
                         "0 skips every oracle run, including the whole n = 16384 sample")
@@ -678,9 +678,9 @@ def main():
     torch.cuda.synchronize()
 
     res = {}
-    precs = {"split6": B.DPP_PREC_SPLIT_BF16X6, "split": B.DPP_PREC_SPLIT_BF16,
-             "fp64": B.DPP_PREC_FP64}
-    order = ["split6", "split", "fp64"] if args.prec == "all" else [args.prec]
+    precs = {"split6": B.DPP_PREC_SPLIT_BF16X6, "fp16": B.DPP_PREC_SPLIT_FP16,
+             "split": B.DPP_PREC_SPLIT_BF16, "fp64": B.DPP_PREC_FP64}
+    order = ["split6", "fp16", "split", "fp64"] if args.prec == "all" else [args.prec]
     for name in order:
         ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F64, [n] * bsz, precs[name]),
                          dtype=torch.uint8, device=dev)
@@ -699,7 +699,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if order[0] == "fp64" else "bf16",
+        "dtype": {"fp64": "f64", "fp16": "f16"}.get(order[0], "bf16"),
         "data": "synthetic",
         "config": {"workload": f"projection kernel K = Q_r Q_r^T, n={n}, rank={r}, FP64 storage; "
                                f"LDL^H sampler, {nsamp} samples per step on streams 2000-{1999 + nsamp} "
@@ -707,8 +707,8 @@ def main():
                                f"of place and writing each sample's factor to its own buffer)",
                    "n": n, "rank": r, "samples_per_step": nsamp, "batch": bsz,
                    "calls": args.calls,
-                   "precision": {"split6": "split_bf16x6", "split": "split_bf16x3",
-                                 "fp64": "fp64"}[order[0]],
+                   "precision": {"split6": "split_bf16x6", "fp16": "split_fp16x3",
+                                 "split": "split_bf16x3", "fp64": "fp64"}[order[0]],
                    "launch": "eager" if args.no_graph else "HIP graph replay of one step"},
         "tflops": round(head["tflops"], 3),
     }
@@ -727,12 +727,13 @@ def main():
                      "pre_decision_d_worst_outside": h["d_worst_out"],
                      "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)}
                                  for k, v in h["profile"].items()}}
-    for name in ("split6", "split"):
+    for name in ("split6", "fp16", "split"):
         if name in res and "fp64" in res:
             out[f"speedup_{name}_vs_fp64"] = round(res[name]["samples_per_s"] /
                                                    res["fp64"]["samples_per_s"], 3)
-    dom_of = {"split6": "update_bf16x6", "split": "update_bf16x3", "fp64": "update_f64"}
-    terms = {"split6": 6, "split": 3}
+    dom_of = {"split6": "update_bf16x6", "fp16": "update_fp16x3", "split": "update_bf16x3",
+              "fp64": "update_f64"}
+    terms = {"split6": 6, "fp16": 3, "split": 3}
 
     def roofline_of(name):
         rl = roofline_entry(res[name]["profile"], dom_of[name],
@@ -741,7 +742,7 @@ def main():
             return None
         rl["traffic"] = measured_traffic(dom_of[name], n, bsz)
         if name in terms:
-            # The split update issues `t` BF16 products per algorithmic one,
+            # The split update issues `t` BF16 (FP16) products per algorithmic one,
             # so 1/t of the peak is its ceiling on the algorithmic count.
             t = terms[name]
             rl["mfma_issued_tflops"] = round(t * rl["achieved"], 3)
@@ -777,7 +778,8 @@ def main():
         # The three-product form is held to 1e-3 over a whole sample at this
         # size (its last pivots reach about 2e-4); the six-product form to the
         # split path's 1e-4.
-        tols = {"split6": (1e-4, 1e-5), "split": (1e-3, 1e-5), "fp64": (1e-9, 1e-10)}
+        tols = {"split6": (1e-4, 1e-5), "fp16": (1e-4, 1e-5), "split": (1e-3, 1e-5),
+                "fp64": (1e-9, 1e-10)}
         for name in order:
             out[name]["vs_oracle"] = parity_entry(res[name]["first"], ref, u0, *tols[name])
             log(f"[bench] {name} vs oracle: {out[name]['vs_oracle']}")

@@ -80,13 +80,25 @@ typedef enum { DPP_F64 = 0, DPP_F32 = 1, DPP_C128 = 2 } dpp_dtype;
    sum is two-level: the matrix cores accumulate 64 values of k at a time,
    and those chunk sums are added up in FP32, so no FP32 sum runs over more
    than max(64, k / 64) terms.
+   DPP_PREC_SPLIT_FP16 (real Hermitian kernels, FP64 or FP32 storage, LDL^H
+   calls only; others return DPP_ERR_INVALID_ARG and workspace size 0): each
+   value is scaled by powers of two (per panel column from its pivot d'_k,
+   so that both factors of a product stay near |w| / sqrt|d'_k|, and per row
+   and 64-column block, to bring the row's largest value near 2^14) and
+   split as hi = fp16(y), lo = fp16(y - hi), about 22 significant bits; the
+   update is hi*hi' + hi*lo' + lo*hi' on FP16 MFMA (the matrix-core work of
+   DPP_PREC_SPLIT_BF16), each 64-value partial sum over k multiplied back by
+   its row and column factors and summed in FP32 as for
+   DPP_PREC_SPLIT_BF16X6. About 2^-22 of each product is lost: between the
+   three- and six-product BF16 forms.
    Every form subtracts the sum from the stored value in the storage
    precision. The diagonal-block decisions, the panel solves and the
    log-likelihood stay in FP64 on every path. */
 typedef enum {
     DPP_PREC_FP64 = 0,
     DPP_PREC_SPLIT_BF16 = 1,
-    DPP_PREC_SPLIT_BF16X6 = 2
+    DPP_PREC_SPLIT_BF16X6 = 2,
+    DPP_PREC_SPLIT_FP16 = 3
 } dpp_precision;
 
 /*

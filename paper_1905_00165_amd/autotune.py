@@ -47,7 +47,7 @@ OBJ = os.path.join(HERE, "_build")
 TUNING = os.path.join(CSRC, "tuning.h")
 
 DEFAULTS = {"kB0LdlhSplit": 4096, "kB0LdlhFp64": 2048, "kB0Lu": 512, "kGroupNarrow": 128,
-            "kGroupSplitN": 2048, "kGroupWide": 1024, "kSmallCutover": [128, 128, 128]}
+            "kGroupSplitN": 2048, "kGroupWide": 1024, "kSmallCutover": [128, 128, 128, 128]}
 
 
 def read_tuning(path=TUNING):
@@ -55,7 +55,7 @@ def read_tuning(path=TUNING):
     vals = {}
     for k, v in DEFAULTS.items():
         if isinstance(v, list):
-            m = re.search(k + r"\[3\] = \{([^}]*)\}", text)
+            m = re.search(k + r"\[4\] = \{([^}]*)\}", text)
             vals[k] = [int(x) for x in m.group(1).split(",")]
         else:
             m = re.search(r"\b" + k + r" = (\d+);", text)
@@ -68,7 +68,7 @@ def render(vals, record):
     out = open(TUNING).read()
     for k, v in vals.items():
         if isinstance(v, list):
-            out = re.sub(k + r"\[3\] = \{[^}]*\}", k + "[3] = {" + ", ".join(str(x) for x in v) + "}", out)
+            out = re.sub(k + r"\[4\] = \{[^}]*\}", k + "[4] = {" + ", ".join(str(x) for x in v) + "}", out)
         else:
             out = re.sub(r"(\b" + k + r" = )\d+;", r"\g<1>" + str(v) + ";", out)
     body = out.split("#pragma once", 1)[1]
@@ -89,7 +89,7 @@ def build_variant(vals, workdir):
     text = open(os.path.join(src, "tuning.h")).read()
     for k, v in vals.items():
         if isinstance(v, list):
-            text = re.sub(k + r"\[3\] = \{[^}]*\}", k + "[3] = {" + ", ".join(str(x) for x in v) + "}", text)
+            text = re.sub(k + r"\[4\] = \{[^}]*\}", k + "[4] = {" + ", ".join(str(x) for x in v) + "}", text)
         else:
             text = re.sub(r"(\b" + k + r" = )\d+;", r"\g<1>" + str(v) + ";", text)
     open(os.path.join(src, "tuning.h"), "w").write(text)
@@ -154,7 +154,7 @@ def _worker(lib, task, arg):
               for i in range(count)]
         us = [torch.from_numpy(W.uniform_stream(n, seed=90000 + i)).to(dev) for i in range(count)]
         As = [torch.empty_like(K) for K in Ks]
-        for prec in (0, 1, 2):
+        for prec in (0, 1, 2, 3):
             ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F32, [n] * count, prec),
                              dtype=torch.uint8, device=dev)
             res[prec] = graph_timed(lambda: B.dpp_sample_ldlh_batched(As, us, prec=prec, ws=ws, Ks=Ks), 10)
@@ -244,20 +244,20 @@ def main():
         B.build()
     base = read_tuning()
     record = [f"Record of the autotune run of {time.strftime('%Y-%m-%d')} (ms per call, by precision 0 = FP64,",
-              "1 = split x3, 2 = split x6):"]
+              "1 = split x3, 2 = split x6, 3 = FP16 split):"]
     chosen = dict(base)
 
     # Small-problem cutover: small path everywhere against blocked everywhere.
     sizes = [32, 64, 96, 128, 160, 192]
-    small_on = dict(base, kSmallCutover=[192, 192, 192])
-    small_off = dict(base, kSmallCutover=[0, 0, 0])
-    cut = [0, 0, 0]
-    faster = [True, True, True]
+    small_on = dict(base, kSmallCutover=[192, 192, 192, 192])
+    small_off = dict(base, kSmallCutover=[0, 0, 0, 0])
+    cut = [0, 0, 0, 0]
+    faster = [True, True, True, True]
     for n in sizes:
         on = measure(small_on, "small", n, log)
         off = measure(small_off, "small", n, log)
         record.append(f"  1024 kernels of n = {n}: small path {on}, blocked {off}")
-        for p in (0, 1, 2):
+        for p in (0, 1, 2, 3):
             faster[p] = faster[p] and on[p] < off[p]
             if faster[p]:
                 cut[p] = n

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdpp.so")
 
 DPP_F64, DPP_F32, DPP_C128 = 0, 1, 2
-DPP_PREC_FP64, DPP_PREC_SPLIT_BF16, DPP_PREC_SPLIT_BF16X6 = 0, 1, 2
+DPP_PREC_FP64, DPP_PREC_SPLIT_BF16, DPP_PREC_SPLIT_BF16X6, DPP_PREC_SPLIT_FP16 = 0, 1, 2, 3
 DPP_OK = 0
 DPP_NOALLOC_SCRATCH_BYTES = 64 << 20   # include/dpp.h
 _STATUS = {0: "DPP_OK", 1: "DPP_ERR_INVALID_ARG", 2: "DPP_ERR_WORKSPACE", 3: "DPP_ERR_HIP",

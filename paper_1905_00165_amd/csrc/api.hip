@@ -44,7 +44,8 @@ struct Plan {
     int dtype;   // 0 FP64 storage, 1 FP32 storage, 2 complex (FP64 parts)
     bool cplx;   // complex: blocks of kLeafC complex columns, real forms in the updates
     int leaf;    // diagonal-block width (kLeaf, or kLeafC for complex)
-    int pieces;  // split-BF16 updates: BF16 pieces per value (2 or 3), 0: FP64 updates
+    int pieces;  // split updates: pieces per value (2 or 3), 0: FP64 updates
+    bool f16;    // the FP16 form (pieces = 2, real Hermitian only)
     int B0;      // outer panel width (leaf times a power of two)
     int ss;      // row stride of the split panel copies (real k columns)
 };
@@ -56,7 +57,8 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     p.dtype = dt == DPP_F32 ? 1 : dt == DPP_C128 ? 2 : 0;
     p.cplx = dt == DPP_C128;
     p.leaf = p.cplx ? dpp::kLeafC : kLeaf;
-    p.pieces = prec == DPP_PREC_SPLIT_BF16 ? 2 : prec == DPP_PREC_SPLIT_BF16X6 ? 3 : 0;
+    p.f16 = prec == DPP_PREC_SPLIT_FP16;
+    p.pieces = prec == DPP_PREC_SPLIT_BF16 || p.f16 ? 2 : prec == DPP_PREC_SPLIT_BF16X6 ? 3 : 0;
     // Outer panel width: each trailing update reads and writes the trailing
     // matrix once, so its HBM traffic per sample is ~ 8 n^3 / (3 B0) bytes for
     // FP64 storage; the split path needs the wider panel to stay MFMA-bound.
@@ -92,20 +94,35 @@ size_t split_bytes(const Plan& p, int64_t n)
     const size_t rows = (size_t)dpp::plane_rows(p.cplx ? 2 * n : n) + (size_t)dpp::plane_rows(n);
     return p.pieces ? align_up((size_t)p.pieces * rows * (size_t)p.ss * sizeof(uint16_t)) : 0;
 }
+// FP16 form: one float per side, row and 64-column block of the panel.
+size_t scale_bytes(const Plan& p, int64_t n)
+{
+    return p.f16 ? align_up(2 * (size_t)(p.ss / 64) * (size_t)dpp::plane_rows(n) * sizeof(float)) : 0;
+}
 size_t diag_bytes(const Plan& p, int64_t n)
 {
     const size_t elt = p.cplx ? 2 * sizeof(double) : sizeof(double);
     return align_up((size_t)((n + p.leaf - 1) / p.leaf) * p.leaf * p.leaf * elt);
 }
-// Per-problem workspace: [diagonal-block strip][split copies].
-size_t problem_bytes(const Plan& p, int64_t n) { return diag_bytes(p, n) + split_bytes(p, n); }
+// Per-problem workspace: [diagonal-block strip][split copies][row scales].
+size_t problem_bytes(const Plan& p, int64_t n)
+{
+    return diag_bytes(p, n) + split_bytes(p, n) + scale_bytes(p, n);
+}
 // Workspace layout: [descriptors][per problem: diagonal strip, split copies].
 size_t desc_bytes(int64_t count) { return align_up((size_t)count * sizeof(DevProb)); }
 
 bool valid_enums(dpp_dtype dt, dpp_precision prec)
 {
     return (dt == DPP_F64 || dt == DPP_F32 || dt == DPP_C128) &&
-           (prec == DPP_PREC_FP64 || prec == DPP_PREC_SPLIT_BF16 || prec == DPP_PREC_SPLIT_BF16X6);
+           (prec == DPP_PREC_FP64 || prec == DPP_PREC_SPLIT_BF16 || prec == DPP_PREC_SPLIT_BF16X6 ||
+            prec == DPP_PREC_SPLIT_FP16);
+}
+// The FP16 form is built for real Hermitian kernels (its column balance uses
+// the bound |w| <= 1 of their Schur complements).
+bool supported(bool herm, dpp_dtype dt, dpp_precision prec)
+{
+    return prec != DPP_PREC_SPLIT_FP16 || (herm && dt != DPP_C128);
 }
 
 // gfx950 check, cached per device ordinal.
@@ -129,12 +146,12 @@ dpp_status device_ok()
 // Kernel families whose launches the profiler tells apart.
 enum KernelId {
     K_LEAF_LDLH, K_LEAF_LU, K_LEAF_ZLDLH, K_LEAF_ZLU, K_UPDATE_F64, K_UPDATE_BF16X3,
-    K_UPDATE_BF16X6, K_SMALL_LDLH, K_STORE_DIAG, K_FINALIZE, K_DESCS, K_COUNT
+    K_UPDATE_BF16X6, K_UPDATE_FP16X3, K_SMALL_LDLH, K_STORE_DIAG, K_FINALIZE, K_DESCS, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"leaf_ldlh",     "leaf_lu",       "leaf_zldlh",
                                            "leaf_zlu",      "update_f64",    "update_bf16x3",
-                                           "update_bf16x6", "small_ldlh",    "store_diag",
-                                           "finalize",      "store_descs"};
+                                           "update_bf16x6", "update_fp16x3", "small_ldlh",
+                                           "store_diag",    "finalize",      "store_descs"};
 
 struct ProfRecord {
     int id;
@@ -250,9 +267,10 @@ dpp_status update(const Ctx& c, const dpp::Region& rg, int64_t k0, int kw, int64
     double fl = 0, by = 0;
     if (c.profiling) update_work(c, rg, kw, fl, by);
     if (c.plan.pieces)
-        return timed(c, c.plan.pieces == 2 ? K_UPDATE_BF16X3 : K_UPDATE_BF16X6, fl, by, [&] {
-            return dpp::launch_update_split(c.plan.herm, c.plan.dtype, c.plan.pieces, c.probs,
-                                            c.spans, c.nspan, rg, k0, kw, j0, c.plan.ss, c.s);
+        return timed(c, c.plan.f16 ? K_UPDATE_FP16X3 : c.plan.pieces == 2 ? K_UPDATE_BF16X3 : K_UPDATE_BF16X6,
+                     fl, by, [&] {
+            return dpp::launch_update_split(c.plan.herm, c.plan.dtype, c.plan.pieces, c.plan.f16,
+                                            c.probs, c.spans, c.nspan, rg, k0, kw, j0, c.plan.ss, c.s);
         });
     return timed(c, K_UPDATE_F64, fl, by, [&] {
         return dpp::launch_update_f64(c.plan.herm, c.plan.dtype, c.probs, c.spans, c.nspan, rg,
@@ -271,8 +289,8 @@ dpp_status leaf(const Ctx& c, int64_t c0, int64_t j0)
         });
     if (c.plan.herm)
         return timed(c, K_LEAF_LDLH, fl, by, [&] {
-            return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.pieces, c.probs, c.spans, c.nspan, c0,
-                                         j0, c.plan.ss, c.s);
+            return dpp::launch_leaf_ldlh(c.plan.dtype, c.plan.pieces, c.plan.f16, c.probs, c.spans,
+                                         c.nspan, c0, j0, c.plan.ss, c.s);
         });
     return timed(c, K_LEAF_LU, fl, by, [&] {
         return dpp::launch_leaf_lu(c.plan.dtype, c.plan.pieces, c.probs, c.spans, c.nspan, c0, j0,
@@ -324,9 +342,9 @@ dpp_status lu_panel(const Ctx& c, int64_t j0)
 
 // Largest n of the small-problem path: the tuned cutover of the precision,
 // or DPP_SMALL_CUTOVER (a decimal in 0..kSmallMax) when that is set.
-int64_t small_cutover(int pieces)
+int64_t small_cutover(const Plan& plan)
 {
-    int64_t cut = dpp::tuned::kSmallCutover[pieces ? pieces - 1 : 0];
+    int64_t cut = dpp::tuned::kSmallCutover[plan.f16 ? 3 : plan.pieces ? plan.pieces - 1 : 0];
     if (const char* e = getenv("DPP_SMALL_CUTOVER")) {
         char* end = nullptr;
         const long v = strtol(e, &end, 10);
@@ -383,7 +401,8 @@ bool source_ok(const dpp_problem& q, dpp_dtype dt)
 dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
                dpp_precision prec, void* ws, size_t ws_bytes, void* stream)
 {
-    if (!probs || count < 1 || count > 65535 || !valid_enums(dt, prec)) return DPP_ERR_INVALID_ARG;
+    if (!probs || count < 1 || count > 65535 || !valid_enums(dt, prec) || !supported(herm, dt, prec))
+        return DPP_ERR_INVALID_ARG;
     int64_t nmax = 0;
     for (int64_t i = 0; i < count; ++i) {
         const dpp_problem& q = probs[i];
@@ -445,6 +464,9 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
         d.diag = reinterpret_cast<double*>(base_of[(size_t)i]);
         d.split = plan.pieces ? reinterpret_cast<uint16_t*>(base_of[(size_t)i] + diag_bytes(plan, q.n))
                               : nullptr;
+        d.scale = plan.f16 ? reinterpret_cast<float*>(base_of[(size_t)i] + diag_bytes(plan, q.n) +
+                                                      split_bytes(plan, q.n))
+                           : nullptr;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     bool profiling;
@@ -471,7 +493,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
     // order) run whole in LDS, one workgroup each, in one launch.
     int64_t nsmall = 0;
     if (plan.herm && !plan.cplx) {
-        const int64_t cut = small_cutover(plan.pieces);
+        const int64_t cut = small_cutover(plan);
         while (nsmall < count && host[(size_t)nsmall].n <= cut) ++nsmall;
     }
     if (nsmall > 0) {
@@ -514,7 +536,7 @@ dpp_status run(bool herm, const dpp_problem* probs, int64_t count, dpp_dtype dt,
 size_t workspace_batched(bool herm, dpp_dtype dt, const int64_t* ns, int64_t count,
                          dpp_precision prec)
 {
-    if (!ns || count < 1 || !valid_enums(dt, prec)) return 0;
+    if (!ns || count < 1 || !valid_enums(dt, prec) || !supported(herm, dt, prec)) return 0;
     int64_t nmax = 0;
     for (int64_t i = 0; i < count; ++i) {
         if (ns[i] < 1 || ns[i] > max_lda(dt)) return 0;

@@ -47,6 +47,7 @@ struct DevProb {
     double* diag;     // ceil(n/64) factored 64x64 diagonal blocks, column-major,
                       // block b at diag[b * 64 * 64]; copied into A at the end
     double* stats;    // 3 decision diagnostics (finalize.hip), or nullptr
+    float* scale;     // FP16 split: per-row scales of the panel copies (below), or nullptr
 };
 
 // Out-of-place calls put the factor in A and leave K untouched. Every entry
@@ -78,6 +79,19 @@ __device__ __forceinline__ const T* first_source(const DevProb& P, bool first, i
 // 1 KiB run; 8 consecutive columns of one row (16 bytes) stay contiguous.
 // For complex kernels the planes of L hold the 2n rows of L' (one per real
 // row of C) and those of B the n rows of W', both with ss real k columns.
+//
+// FP16 form (real LDL^H): np = 2 planes per side hold FP16 pieces hi =
+// fp16(y), lo = fp16(y - hi) of scaled values y. Column k of the panel is
+// balanced by a power of two rho_k near sqrt|d'_k|: the L side holds l_ik rho_k
+// and the B side w_ik / rho_k, so their products are those of L and W while
+// both sides stay near |w| / sqrt|d'_k| (every |w_ik| <= 1 for a marginal
+// kernel); then each row's 64 values of one 64-column block are multiplied
+// by the power of two 2^e that brings their largest magnitude into
+// (2^13, 2^14], which keeps FP16's 11 bits for every value within 2^17 of the
+// row's largest. The factor 2^-e that undoes it is kept per side s (0: L,
+// 1: B), block c (kk / 64) and row r at scale[scale_off(n, ss, s, c, r)]; an
+// update multiplies each 64-k partial sum of C by the factors of its row and
+// column.
 __host__ __device__ inline int64_t plane_rows(int64_t n) { return (n + 31) / 32 * 32; }
 __host__ __device__ inline uint16_t* split_plane(uint16_t* base, int64_t nl, int64_t nb, int ss,
                                                  int np, int q)
@@ -88,6 +102,10 @@ __host__ __device__ inline uint16_t* split_plane(uint16_t* base, int64_t nl, int
 __host__ __device__ inline uint16_t* split_plane(uint16_t* base, int64_t n, int ss, int q)
 {
     return base + (int64_t)q * plane_rows(n) * ss;
+}
+__host__ __device__ inline int64_t scale_off(int64_t n, int ss, int side, int c, int64_t r)
+{
+    return ((int64_t)side * (ss / 64) + c) * plane_rows(n) + r;
 }
 __host__ __device__ inline int64_t plane_off(int64_t r, int kk, int ss)
 {
@@ -139,9 +157,11 @@ __device__ __forceinline__ int64_t xcd_order(int64_t i, int64_t G) { return (i %
 // Diagonal block [c0, c0+64) of every problem: decisions, L11/D1 (or L11/U11),
 // and the panel solves for the rows below it (LU: and the columns to its
 // right). With pieces = 2 or 3 also writes that many split-BF16 pieces of
-// each panel value (0: none) at outer panel offset j0 with row stride ss.
-hipError_t launch_leaf_ldlh(int dtype, int pieces, const DevProb* probs, const GroupSpan* spans,
-                            int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s);
+// each panel value (0: none) at outer panel offset j0 with row stride ss;
+// leaf_ldlh with f16 (pieces = 2) writes the FP16 form and its row scales.
+hipError_t launch_leaf_ldlh(int dtype, int pieces, bool f16, const DevProb* probs,
+                            const GroupSpan* spans, int nspan, int64_t c0, int64_t j0, int ss,
+                            hipStream_t s);
 hipError_t launch_leaf_lu(int dtype, int pieces, const DevProb* probs, const GroupSpan* spans,
                           int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s);
 // Complex kernels (storage dtype 2): the diagonal block [c0, c0 + kLeafC) in
@@ -170,10 +190,12 @@ inline Region trailing_region(int64_t base, int64_t ncols)
 hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, const GroupSpan* spans,
                              int nspan, Region rg, int64_t k0, int kw, hipStream_t s);
 // Split-BF16 form: the products of the `pieces` (2 or 3) BF16 pieces of L and
-// B whose orders sum to at most pieces - 1 (3 or 6 MFMA products).
+// B whose orders sum to at most pieces - 1 (3 or 6 MFMA products). f16 (real
+// Hermitian, pieces = 2): the FP16 form, hi*hi' + hi*lo' + lo*hi' on FP16
+// MFMA, each 64-k partial sum scaled by its row and column factors.
 // Groups whose updated columns call for different tile shapes go to separate
 // launches (at most three).
-hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs,
+hipError_t launch_update_split(bool herm, int dtype, int pieces, bool f16, const DevProb* probs,
                                const GroupSpan* spans, int nspan, Region rg, int64_t k0, int kw,
                                int64_t j0, int ss, hipStream_t s);
 
@@ -198,7 +220,7 @@ hipError_t launch_store_diag(bool herm, int dtype, const DevProb* probs, int npr
 
 // Copy `cnt` (<= kDescPerLaunch) host descriptors to dst through the kernel
 // argument block of a one-workgroup launch.
-constexpr int kDescPerLaunch = 36;  // 36 descriptors + count fit the 4 KiB argument block
+constexpr int kDescPerLaunch = 34;  // 34 descriptors + count fit the 4 KiB argument block
 hipError_t launch_store_descs(const DevProb* host, int cnt, DevProb* dst, hipStream_t s);
 
 // L-ensemble conversion (lensemble.hip): one problem's device descriptor.

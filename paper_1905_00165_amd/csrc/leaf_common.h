@@ -217,6 +217,52 @@ __device__ __forceinline__ void store_pieces8(uint16_t* base, int64_t n, int ss,
     store_pieces8_at<NPC>(split_plane(base, n, ss, q0), plane_rows(n) * ss, ss, r, kk, v);
 }
 
+// FP16 form: hi = fp16(y), lo = fp16(y - hi) of 8 consecutive (already
+// scaled) values y[0..7] of row r, columns kk .. kk+7 of the outer panel;
+// piece i goes to the plane at first + i * stride, one 16-byte store each.
+__device__ __forceinline__ void store_f16_pieces8_at(uint16_t* first, int64_t stride, int ss,
+                                                     int64_t r, int kk, const double (&y)[8])
+{
+    uint32_t w[2][4];
+#pragma unroll
+    for (int p2 = 0; p2 < 4; ++p2) {
+        uint32_t h[2], l[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const double v = y[2 * p2 + t];
+            const _Float16 hi = (_Float16)v;
+            const _Float16 lo = (_Float16)(v - (double)hi);
+            h[t] = __builtin_bit_cast(uint16_t, hi);
+            l[t] = __builtin_bit_cast(uint16_t, lo);
+        }
+        w[0][p2] = h[0] | (h[1] << 16);
+        w[1][p2] = l[0] | (l[1] << 16);
+    }
+    const int64_t o = plane_off(r, kk, ss);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        *reinterpret_cast<uint4*>(first + i * stride + o) = make_uint4(w[i][0], w[i][1], w[i][2], w[i][3]);
+}
+
+// The FP16 form's column balance rho = 2^h, h = floor(x / 2) for |d'| in
+// [2^(x-1), 2^x) (about sqrt|d'|; 1 for d' = 0), so that l rho = (w / d') rho
+// and w / rho are both near |w| / sqrt|d'|; and the exponent e that brings a
+// row block's largest magnitude m into (2^13, 2^14] (0 for m = 0).
+__device__ __forceinline__ double f16_rho(double d)
+{
+    if (d == 0.0) return 1.0;
+    int x;
+    (void)__builtin_frexp(d, &x);
+    return __builtin_ldexp(1.0, x >> 1);
+}
+__device__ __forceinline__ int f16_row_exp(double m)
+{
+    if (!(m > 0.0)) return 0;
+    int x;
+    const double f = __builtin_frexp(m, &x);  // m = f 2^x, f in [0.5, 1): m <= 2^x, > 2^(x-1)
+    return 14 - (f == 0.5 ? x - 1 : x);
+}
+
 // ------------------------------------------------------------ panel solves
 // Rows of a panel solved against the factored 64x64 diagonal block on the
 // matrix cores. A solve of the form X T^T = A (T lower triangular, 64 x 64)

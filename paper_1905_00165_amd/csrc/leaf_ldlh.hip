@@ -24,8 +24,10 @@ using namespace leaf;
 // the right-hand operand of the next, and a row group never leaves registers.
 // The four inverses L_bb^{-1} (unit lower triangular) are formed once per
 // workgroup by forward substitution, one column per lane.
-// Then L21 = W D1^{-1}; A receives L21, the split planes W and L21.
-template <typename T, int NPC>
+// Then L21 = W D1^{-1}; A receives L21, the split planes W and L21 (F16:
+// their FP16 form, dpp_internal.h: each column balanced by rho_k, each row's
+// 64 values of this block normalised by 2^e, the factor 2^-e kept per row).
+template <typename T, int NPC, bool F16>
 __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restrict__ probs, GroupMap M,
                                                int64_t c0, int64_t j0, int ss)
 {
@@ -51,6 +53,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
     __shared__ __attribute__((aligned(16))) double smem[kSmem];
     double* const sB = smem;               // chain: broadcast columns of the current two pivots
     double* const sR = smem + L;           // 1 / D1 (written after the chain, over sB's second half)
+    double* const sRho = smem;             // F16: column balance (after the chain, sB's first half)
     double* const sL = smem + 2 * L;       // sL[t*kBP + k] = L11[k][t] for k > t, zero elsewhere
     double* const sI = sL + L * kBP;       // the inverses of L11's 16 x 16 diagonal blocks
     double* const sT = sI + 4 * kInvBlock;  // per wavefront: W of one row group, row-major
@@ -144,6 +147,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
 #pragma unroll
         for (int k = 0; k < L; ++k) sL[k * kBP + lane] = (k < lane && lane < bs) ? a[k] : 0.0;
         sR[lane] = (lane < bs) ? 1.0 / mydp : 1.0;
+        if constexpr (F16) sRho[lane] = (lane < bs) ? f16_rho(mydp) : 1.0;
 
         // The factored block goes to the workspace strip, not to A: other
         // workgroups of this launch may still be loading the original block
@@ -216,8 +220,49 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
             __builtin_amdgcn_wave_barrier();
             const int tr = lane >> 2, tc = 8 * (lane & 3);
             const int64_t rr = wrow0 + 16 * g + tr;
-            if (rr < n) {
-                const int kk = (int)(c0 - j0) + tc;
+            const int kk = (int)(c0 - j0) + tc;
+            if constexpr (F16) {
+                // Row rr's 64 values sit in lanes 4 tr .. 4 tr + 3 (16 each):
+                // balance, then the block maximum of each side over those lanes.
+                double wv[2][8], lv[2][8];
+                double mw = 0.0, ml = 0.0;
+#pragma unroll
+                for (int half = 0; half < 2; ++half)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int col = 32 * half + tc + c;
+                        const double w = tile[tr * kTilePitch + col], rho = sRho[col];
+                        wv[half][c] = w / rho;                // W / rho (exact: a power of two)
+                        lv[half][c] = w * sR[col] * rho;      // L rho
+                        mw = __builtin_fmax(mw, __builtin_fabs(wv[half][c]));
+                        ml = __builtin_fmax(ml, __builtin_fabs(lv[half][c]));
+                    }
+                mw = __builtin_fmax(mw, __shfl_xor(mw, 1));
+                mw = __builtin_fmax(mw, __shfl_xor(mw, 2));
+                ml = __builtin_fmax(ml, __shfl_xor(ml, 1));
+                ml = __builtin_fmax(ml, __shfl_xor(ml, 2));
+                const int ew = f16_row_exp(mw), el = f16_row_exp(ml);
+                if (rr < n) {
+                    const int64_t pst = plane_rows(n) * (int64_t)ss;
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            wv[half][c] = __builtin_ldexp(wv[half][c], ew);
+                            lv[half][c] = __builtin_ldexp(lv[half][c], el);
+                        }
+                        store_f16_pieces8_at(split_plane(P.split, n, ss, 2), pst, ss, rr, kk + 32 * half,
+                                             wv[half]);
+                        store_f16_pieces8_at(split_plane(P.split, n, ss, 0), pst, ss, rr, kk + 32 * half,
+                                             lv[half]);
+                    }
+                    if ((lane & 3) == 0) {
+                        const int blk = (int)((c0 - j0) / L);
+                        P.scale[scale_off(n, ss, 0, blk, rr)] = (float)__builtin_ldexp(1.0, -el);
+                        P.scale[scale_off(n, ss, 1, blk, rr)] = (float)__builtin_ldexp(1.0, -ew);
+                    }
+                }
+            } else if (rr < n) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     double wv[8], lv[8];
@@ -245,28 +290,30 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
 }
 
 template <typename T>
-hipError_t launch_t(int pieces, const DevProb* probs, const GroupSpan* spans, int nspan, int64_t c0,
-                    int64_t j0, int ss, hipStream_t s)
+hipError_t launch_t(int pieces, bool f16, const DevProb* probs, const GroupSpan* spans, int nspan,
+                    int64_t c0, int64_t j0, int ss, hipStream_t s)
 {
     GroupMap M;
     const int64_t total = leaf_map(spans, nspan, c0, L, 2, M);  // two workgroups per CU
     if (total == 0) return hipSuccess;
     dim3 grid((unsigned)total), block(kThreads);
-    if (pieces == 3) hipLaunchKernelGGL((leaf_ldlh<T, 3>), grid, block, 0, s, probs, M, c0, j0, ss);
-    else if (pieces == 2) hipLaunchKernelGGL((leaf_ldlh<T, 2>), grid, block, 0, s, probs, M, c0, j0, ss);
-    else hipLaunchKernelGGL((leaf_ldlh<T, 0>), grid, block, 0, s, probs, M, c0, j0, ss);
+    if (f16) hipLaunchKernelGGL((leaf_ldlh<T, 2, true>), grid, block, 0, s, probs, M, c0, j0, ss);
+    else if (pieces == 3) hipLaunchKernelGGL((leaf_ldlh<T, 3, false>), grid, block, 0, s, probs, M, c0, j0, ss);
+    else if (pieces == 2) hipLaunchKernelGGL((leaf_ldlh<T, 2, false>), grid, block, 0, s, probs, M, c0, j0, ss);
+    else hipLaunchKernelGGL((leaf_ldlh<T, 0, false>), grid, block, 0, s, probs, M, c0, j0, ss);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_leaf_ldlh(int dtype, int pieces, const DevProb* probs, const GroupSpan* spans,
-                            int nspan, int64_t c0, int64_t j0, int ss, hipStream_t s)
+hipError_t launch_leaf_ldlh(int dtype, int pieces, bool f16, const DevProb* probs,
+                            const GroupSpan* spans, int nspan, int64_t c0, int64_t j0, int ss,
+                            hipStream_t s)
 {
-    if (pieces != 0 && pieces != 2 && pieces != 3) return hipErrorInvalidValue;
+    if ((pieces != 0 && pieces != 2 && pieces != 3) || (f16 && pieces != 2)) return hipErrorInvalidValue;
     if (nspan > kMaxGroupsPerLaunch) return hipErrorInvalidValue;
-    if (dtype == 0) return launch_t<double>(pieces, probs, spans, nspan, c0, j0, ss, s);
-    return launch_t<float>(pieces, probs, spans, nspan, c0, j0, ss, s);
+    if (dtype == 0) return launch_t<double>(pieces, f16, probs, spans, nspan, c0, j0, ss, s);
+    return launch_t<float>(pieces, f16, probs, spans, nspan, c0, j0, ss, s);
 }
 
 }  // namespace dpp

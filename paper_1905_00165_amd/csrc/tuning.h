@@ -46,8 +46,8 @@ constexpr int64_t kGroupWide = 1024;
 
 // Largest n of a real Hermitian problem that runs in one workgroup with the
 // whole lower triangle in registers (small_ldlh.hip), by precision (FP64, split x3, split
-// x6); 0 disables the path. At most kSmallMax.
-constexpr int64_t kSmallCutover[3] = {0, 0, 0};
+// x6, FP16 split); 0 disables the path. At most kSmallMax.
+constexpr int64_t kSmallCutover[4] = {0, 0, 0, 0};
 
 }  // namespace tuned
 }  // namespace dpp

@@ -15,6 +15,15 @@
 //     zero, and each such chunk sum is added into a second FP32 total, so no
 //     FP32 sum runs over more than max(64, kw / 64) terms. Both sets fit two
 //     wavefronts per SIMD (64 x 64 per wavefront).
+//   FP16 form (update_fp16x3, real LDL^H): hi*hi' + hi*lo' + lo*hi' on
+//     v_mfma_f32_32x32x16_f16 over the FP16 pieces of balanced, row-scaled
+//     values (dpp_internal.h). FP16's 11 bits make the pieces carry 22 bits
+//     of each value, but only relative to its row's 64-column block: so the
+//     MFMAs run 64 k at a time, and each chunk sum is multiplied by its row's
+//     and its column's factors (powers of two: exact) and added into FP32
+//     totals. The factors of a chunk are loaded into registers at its first
+//     stage, before that stage's copies, so the stage waits below also cover
+//     them one stage later.
 // The sum is subtracted from the stored value in FP64 and rounded to the
 // storage type.
 //
@@ -56,6 +65,8 @@ namespace {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 typedef const void __attribute__((address_space(1)))* gptr_t;
 typedef void __attribute__((address_space(3)))* lptr_t;
 
@@ -66,9 +77,10 @@ constexpr int kGroupCols = 4;      // tile columns per group of the wide order
 // stages (NST - 1 of them in flight while one is multiplied); NP BF16 pieces
 // per operand value. FL > 0: the FP32 accumulators are added into FP32
 // totals (and restart from zero) every FL stages, so no MFMA chain runs over
-// more than FL * KC values of k.
+// more than FL * KC values of k. F16: the FP16 form (NP = 2, FL * KC = 64,
+// one chunk per 64-column block of the row factors).
 template <int TM_, int TN_, int WR_, int WC_, int MINB_, int EP_, int KC_, int NST_, int NP_,
-          int FL_ = 0>
+          int FL_ = 0, bool F16_ = false>
 struct Shape {
     static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_;
     static constexpr int MINB = MINB_;  // workgroups per CU the register budget allows
@@ -76,6 +88,7 @@ struct Shape {
     static constexpr int KC = KC_, NST = NST_;
     static constexpr int NP = NP_;                                 // pieces per value
     static constexpr int FL = FL_;                                 // stages per chunk (0: one chain)
+    static constexpr bool F16 = F16_;
     static constexpr int NTERM = NP == 2 ? 3 : 6;                  // product terms
     static constexpr int ROWB = KC * 2;                            // bytes per operand row and stage
     static constexpr int KSTEPS = KC / 16;                         // MFMA k steps per stage
@@ -96,6 +109,7 @@ struct Shape {
     static_assert(A_PLANE % 1024 == 0 && W_PLANE % 1024 == 0, "no copy straddles two planes");
     static_assert(LDS <= 160 * 1024 / MINB, "LDS of MINB workgroups per CU");
     static_assert(NST >= 2 && NST <= 4, "vmcnt bookkeeping covers 2..4 stages");
+    static_assert(!F16 || (NP == 2 && FL * KC == 64), "FP16 form: chunks are the 64-column blocks");
 };
 // (L piece, W piece) of product term t: the pairs whose orders sum to at most
 // NP - 1, larger terms first.
@@ -110,6 +124,9 @@ using Narrow3 = Shape<128, 64, 4, 1, 3, 1, 32, 2, 2>;
 using Wide6 = Shape<128, 128, 2, 2, 2, 1, 16, 3, 3, 4>;
 using Medium6 = Wide6;
 using Narrow6 = Shape<128, 64, 4, 1, 2, 1, 32, 2, 3, 2>;
+// FP16 form: chunks of 64 k scaled into FP32 totals, as the six products.
+using Wide16 = Shape<128, 128, 2, 2, 2, 1, 16, 3, 2, 4, true>;
+using Narrow16 = Shape<128, 64, 4, 1, 2, 1, 32, 2, 2, 2, true>;
 
 // MFMAs spread evenly over the READS fragment reads that follow the first
 // group: slot r gets floor((r+1) M / R) - floor(r M / R) MFMAs, then one read.
@@ -344,6 +361,35 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acct[rb][cb][e] = 0.0f;
     }
+    // FP16 form: the factors of the current chunk for this lane's rows (one
+    // per row block) and columns (16 per column block, in four runs of 4
+    // consecutive columns: the accumulator layout below). Rows and column
+    // runs past the region read the last valid ones; they only scale
+    // accumulators that are never stored.
+    constexpr int NSCALE = S::F16 ? S::RB + 4 * S::CB : 0;  // loads per chunk
+    float rsv[S::F16 ? S::RB : 1];
+    f4v csv[S::F16 ? S::CB : 1][4];
+    auto load_scales = [&](int st) {
+        if constexpr (S::F16) {
+            const int c = (kk0 + st * S::KC) / 64;  // the chunk's 64-column block
+#pragma unroll
+            for (int rb = 0; rb < S::RB; ++rb) {
+                int64_t g = rowT0 + wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
+                g = g < rEnd - 1 ? g : rEnd - 1;
+                rsv[rb] = P.scale[scale_off(n, ss, 0, c, g)];
+            }
+            const int64_t last4 = (colEnd - 1) & ~(int64_t)3;
+#pragma unroll
+            for (int cb = 0; cb < S::CB; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int64_t g = colT0 + wc * (S::TN / S::WC) + cb * 32 + 8 * q + 4 * (lane >> 5);
+                    g = g < last4 ? g : last4;
+                    csv[cb][q] = *reinterpret_cast<const f4v*>(P.scale + scale_off(n, ss, 1, c, g));
+                }
+        }
+    };
+
     // The value of the update at accumulator element e of block (rb, cb).
     auto acc_value = [&](int rb, int cb, int e) -> double {
         if constexpr (TWO_LEVEL) return (double)acct[rb][cb][e];
@@ -441,10 +487,17 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     };
 
     double cva[CP][16], cvb[CP][16];
+    // The single-chain form with two pieces has the registers to load the
+    // first C round during its last stage; every other form loads it after
+    // the loop.
+    constexpr bool C_PREFETCH = S::NP == 2 && !TWO_LEVEL;
     for (int p = 0; p < S::NST - 1; ++p) issue_stage(p);
     // One stage: wait for its copies, refill the buffer freed last, then its
     // k steps on the matrix cores.
-    auto stage = [&](int st, bool prefetch_c) {
+    // first_c (std::bool_constant): the first stage of an FP16 chunk, which
+    // also loads the chunk's factors.
+    auto stage = [&](int st, bool prefetch_c, auto first_c) {
+        constexpr bool LOAD_SCALES = S::F16 && decltype(first_c)::value;
         const int buf = st % S::NST;
         // This wavefront's copies of stage st are in LDS (the NST - 2 later
         // stages already issued may still be in flight); the barrier makes
@@ -458,17 +511,17 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         // the MFMAs that consumed them. The memory clobber keeps the compiler
         // from moving LDS accesses across the barrier.
         asm volatile("s_barrier" ::: "memory");
-        // First C round in flight during the last stage (with three pieces
-        // the fragments leave no registers for it: loaded after the loop).
-        if (S::NP == 2 && prefetch_c) c_load(0, cva);
+        // First C round in flight during the last stage (C_PREFETCH).
+        if (C_PREFETCH && prefetch_c) c_load(0, cva);
         const unsigned char* B0 = lds + buf * S::BUF;
-        bf8 lp[S::NP][S::KSTEPS][S::RB], wp[S::NP][S::KSTEPS][S::CB];
+        using Frag = std::conditional_t<S::F16, h8, bf8>;
+        Frag lp[S::NP][S::KSTEPS][S::RB], wp[S::NP][S::KSTEPS][S::CB];
         auto read_l = [&](int p, int ks) {
             const int seg = ks * 2 + (lane >> 5);  // 8 k values per lane
 #pragma unroll
             for (int b = 0; b < S::RB; ++b) {
                 const int ra = wr * (S::TM / S::WR) + b * 32 + (lane & 31);
-                lp[p][ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + p * S::A_PLANE + lds_off<S::ROWB>(ra, seg)));
+                lp[p][ks][b] = __builtin_bit_cast(Frag, *reinterpret_cast<const uint4*>(B0 + p * S::A_PLANE + lds_off<S::ROWB>(ra, seg)));
             }
         };
         auto read_w = [&](int p, int ks) {
@@ -476,7 +529,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
 #pragma unroll
             for (int b = 0; b < S::CB; ++b) {
                 const int rc = wc * (S::TN / S::WC) + b * 32 + (lane & 31);
-                wp[p][ks][b] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4*>(B0 + S::NP * S::A_PLANE + p * S::W_PLANE + lds_off<S::ROWB>(rc, seg)));
+                wp[p][ks][b] = __builtin_bit_cast(Frag, *reinterpret_cast<const uint4*>(B0 + S::NP * S::A_PLANE + p * S::W_PLANE + lds_off<S::ROWB>(rc, seg)));
             }
         };
         // Fragments in the order the MFMAs below consume them: L0, W0, W1, L1
@@ -499,11 +552,17 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
 #pragma unroll
                 for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
-                    for (int cb = 0; cb < S::CB; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], acc[rb][cb], 0, 0, 0);
+                    for (int cb = 0; cb < S::CB; ++cb) {
+                        if constexpr (S::F16)
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], acc[rb][cb], 0, 0, 0);
+                        else
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], acc[rb][cb], 0, 0, 0);
+                    }
         };
         if constexpr (S::KSTEPS == 2) {
+            if constexpr (LOAD_SCALES) load_scales(st);
             read_frags(0);
             read_frags(1);
             // The next stage's copies after this stage's fragment reads (they
@@ -512,10 +571,11 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
             issue_stage(st + S::NST - 1);
             mfmas(0);
             mfmas(1);
-            // Schedule: k step 0's fragment reads, then its MFMAs with k step
-            // 1's reads interleaved evenly, then k step 1's MFMAs with the
-            // next stage's copies in between.
+            // Schedule: (a chunk's factors,) k step 0's fragment reads, then
+            // its MFMAs with k step 1's reads interleaved evenly, then k step
+            // 1's MFMAs with the next stage's copies in between.
             static_assert(S::MFMAS >= S::PER_WAVE, "a product per copy");
+            if constexpr (LOAD_SCALES) __builtin_amdgcn_sched_group_barrier(0x020, NSCALE, 0);  // VMEM read
             __builtin_amdgcn_sched_group_barrier(0x100, S::READS, 0);  // DS read
             interleave_mfma_reads<S::MFMAS, S::READS>();
             for (int q = 0; q < S::PER_WAVE; ++q) {
@@ -524,14 +584,17 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
             }
             __builtin_amdgcn_sched_group_barrier(0x008, S::MFMAS - S::PER_WAVE, 0);
         } else {
+            if constexpr (LOAD_SCALES) load_scales(st);
             read_frags(0);
             issue_stage(st + S::NST - 1);  // after the fragment reads, as above
             mfmas(0);
-            // Schedule: the fragments of the first product term (p0 x p0'),
-            // then its MFMAs with the remaining fragment reads interleaved,
-            // then the next stage's copies between further MFMAs.
+            // Schedule: (a chunk's factors,) the fragments of the first
+            // product term (p0 x p0'), then its MFMAs with the remaining
+            // fragment reads interleaved, then the next stage's copies between
+            // further MFMAs.
             constexpr int first = S::RB + S::CB, rest = S::READS - first;
             static_assert(S::MFMAS - rest >= S::PER_WAVE, "a product per copy");
+            if constexpr (LOAD_SCALES) __builtin_amdgcn_sched_group_barrier(0x020, NSCALE, 0);  // VMEM read
             __builtin_amdgcn_sched_group_barrier(0x100, first, 0);
             for (int r = 0; r < rest; ++r) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -553,21 +616,30 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         // to and from the MFMA's accumulation registers every stage.
         for (int s0 = 0; s0 < nstages; s0 += S::FL) {
             const int s1 = s0 + S::FL < nstages ? s0 + S::FL : nstages;
-            for (int st = s0; st < s1; ++st) stage(st, false);
+            if constexpr (S::F16) {
+                stage(s0, false, std::true_type{});
+                for (int st = s0 + 1; st < s1; ++st) stage(st, false, std::false_type{});
+            } else {
+                for (int st = s0; st < s1; ++st) stage(st, false, std::false_type{});
+            }
 #pragma unroll
             for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < S::CB; ++cb)
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
-                        acct[rb][cb][e] += acc[rb][cb][e];
+                        if constexpr (S::F16)  // the factors are powers of two: the product is exact
+                            acct[rb][cb][e] = __builtin_fmaf(acc[rb][cb][e], rsv[rb] * csv[cb][e >> 2][e & 3],
+                                                             acct[rb][cb][e]);
+                        else
+                            acct[rb][cb][e] += acc[rb][cb][e];
                         acc[rb][cb][e] = 0.0f;
                     }
         }
     } else {
         // The last stage apart: it also starts the first C round's loads.
-        for (int st = 0; st < nstages - 1; ++st) stage(st, false);
-        stage(nstages - 1, true);
+        for (int st = 0; st < nstages - 1; ++st) stage(st, false, std::false_type{});
+        stage(nstages - 1, true, std::false_type{});
     }
     // The copies issued past the last stage still write LDS: drain them
     // before the workgroup can end.
@@ -584,19 +656,19 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     for (int r = 0; r < ROUNDS; ++r) {
         double (&cur)[CP][16] = (r & 1) ? cvb : cva;
         double (&nxt)[CP][16] = (r & 1) ? cva : cvb;
-        if (S::NP == 3 && r == 0) c_load(0, cur);
+        if (!C_PREFETCH && r == 0) c_load(0, cur);
         if (r + 1 < ROUNDS) c_load(r + 1, nxt);
         c_store(r, cur);
     }
 }
 
-// The two product forms as separate kernels, so that profiles tell them apart.
+// The product forms as separate kernels, so that profiles tell them apart.
 template <typename T, bool HERM, class S, bool CPLX>
 __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x3(const DevProb* __restrict__ probs,
                                                                      GroupMap M, Region rg, int64_t k0,
                                                                      int kw, int64_t j0, int ss)
 {
-    static_assert(S::NP == 2, "three products from two pieces");
+    static_assert(S::NP == 2 && !S::F16, "three products from two pieces");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     update_body<T, HERM, S, CPLX>(probs, M, rg, k0, kw, j0, ss, lds);
 }
@@ -611,9 +683,20 @@ __global__ __launch_bounds__(S::THREADS, S::MINB) void update_bf16x6(const DevPr
 }
 
 template <typename T, bool HERM, class S, bool CPLX>
+__global__ __launch_bounds__(S::THREADS, S::MINB) void update_fp16x3(const DevProb* __restrict__ probs,
+                                                                     GroupMap M, Region rg, int64_t k0,
+                                                                     int kw, int64_t j0, int ss)
+{
+    static_assert(S::F16 && HERM && !CPLX, "the FP16 form serves real Hermitian problems");
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    update_body<T, HERM, S, CPLX>(probs, M, rg, k0, kw, j0, ss, lds);
+}
+
+template <typename T, bool HERM, class S, bool CPLX>
 constexpr auto kernel_of()
 {
-    if constexpr (S::NP == 2) return update_bf16x3<T, HERM, S, CPLX>;
+    if constexpr (S::F16) return update_fp16x3<T, HERM, S, CPLX>;
+    else if constexpr (S::NP == 2) return update_bf16x3<T, HERM, S, CPLX>;
     else return update_bf16x6<T, HERM, S, CPLX>;
 }
 
@@ -658,13 +741,13 @@ hipError_t launch_shape(const DevProb* probs, const GroupSpan* spans, int nspan,
 
 // The tile shape follows the width of each group's updated column range;
 // groups of one shape share a launch.
-template <typename T, bool HERM, int NP, bool CPLX>
+template <typename T, bool HERM, int NP, bool CPLX, bool F16 = false>
 hipError_t launch_t(const DevProb* probs, const GroupSpan* spans, int nspan, Region rg, int64_t k0,
                     int kw, int64_t j0, int ss, hipStream_t s)
 {
-    using Narrow = std::conditional_t<NP == 2, Narrow3, Narrow6>;
-    using Medium = std::conditional_t<NP == 2, Medium3, Medium6>;
-    using Wide = std::conditional_t<NP == 2, Wide3, Wide6>;
+    using Narrow = std::conditional_t<F16, Narrow16, std::conditional_t<NP == 2, Narrow3, Narrow6>>;
+    using Medium = std::conditional_t<F16, Wide16, std::conditional_t<NP == 2, Medium3, Medium6>>;
+    using Wide = std::conditional_t<F16, Wide16, std::conditional_t<NP == 2, Wide3, Wide6>>;
     GroupSpan by[3][kMaxGroupsPerLaunch];
     int cnt[3] = {0, 0, 0};
     for (int i = 0; i < nspan; ++i) {
@@ -702,7 +785,7 @@ hipError_t launch_np(bool herm, int dtype, const DevProb* probs, const GroupSpan
 
 }  // namespace
 
-hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* probs,
+hipError_t launch_update_split(bool herm, int dtype, int pieces, bool f16, const DevProb* probs,
                                const GroupSpan* spans, int nspan, Region rg, int64_t k0, int kw,
                                int64_t j0, int ss, hipStream_t s)
 {
@@ -710,6 +793,12 @@ hipError_t launch_update_split(bool herm, int dtype, int pieces, const DevProb* 
     if ((kw * (dtype == 2 ? 2 : 1)) % kKAlign != 0 || (herm && rg.r0 != rg.c0) ||
         nspan > kMaxGroupsPerLaunch)
         return hipErrorInvalidValue;
+    if (f16) {
+        // Real Hermitian only; chunks start on the 64-column blocks of the factors.
+        if (!herm || dtype == 2 || pieces != 2 || (k0 - j0) % 64 != 0) return hipErrorInvalidValue;
+        if (dtype == 0) return launch_t<double, true, 2, false, true>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
+        return launch_t<float, true, 2, false, true>(probs, spans, nspan, rg, k0, kw, j0, ss, s);
+    }
     if (pieces == 2) return launch_np<2>(herm, dtype, probs, spans, nspan, rg, k0, kw, j0, ss, s);
     if (pieces == 3) return launch_np<3>(herm, dtype, probs, spans, nspan, rg, k0, kw, j0, ss, s);
     return hipErrorInvalidValue;

@@ -206,7 +206,22 @@ def test_six_product_workspace_holds_six_planes():
     s6 = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_SPLIT_BF16X6)
     planes = 1024 * 1024 * 2   # rows padded to 32, columns to the 64-wide blocks
     assert s3 - f == 4 * planes and s6 - f == 6 * planes
-    assert B.dpp_workspace_size(True, B.DPP_F64, 1000, 3) == 0   # unknown precision
+    assert B.dpp_workspace_size(True, B.DPP_F64, 1000, 4) == 0   # unknown precision
+
+
+def test_fp16_workspace_holds_four_planes_and_row_factors():
+    """DPP_PREC_SPLIT_FP16 keeps two FP16 pieces of L and of W (four planes)
+    and one FP32 factor per row, side and 64-column block; it serves real
+    Hermitian problems only (LU and complex kernels: size 0, i.e. invalid)."""
+    f = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_FP64)
+    s16 = B.dpp_workspace_size(True, B.DPP_F64, 1000, B.DPP_PREC_SPLIT_FP16)
+    planes = 1024 * 1024 * 2
+    factors = 2 * (1024 // 64) * 1024 * 4   # sides x blocks x padded rows x FP32
+    assert s16 - f == 4 * planes + factors
+    assert B.dpp_workspace_size(True, B.DPP_F32, 1000, B.DPP_PREC_SPLIT_FP16) > 0
+    assert B.dpp_workspace_size(False, B.DPP_F64, 1000, B.DPP_PREC_SPLIT_FP16) == 0
+    assert B.dpp_workspace_size(True, B.DPP_C128, 1000, B.DPP_PREC_SPLIT_FP16) == 0
+    assert B.dpp_workspace_size(False, B.DPP_C128, 1000, B.DPP_PREC_SPLIT_FP16) == 0
 
 
 def test_noalloc_argument_errors_return_before_any_launch():

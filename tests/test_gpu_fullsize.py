@@ -23,6 +23,8 @@ form keeps about 16 bits of each product; over a whole sample at this size
 its last pivots (the conditional kernel there is a nearly exhausted
 projection) amplify that to about 2e-4, so its full-length comparison is held
 to 1e-3 and the six-product form is the split path held to 1e-4 at this size.
+The FP16 form (pieces relative to each row's 64-column block, 22 bits of
+each value) is held to 1e-4 throughout.
 """
 import numpy as np
 import pytest
@@ -35,10 +37,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 N, RANK, BATCH = 16384, 4096, 8
-TOL = {0: 1e-9, 1: 1e-4, 2: 1e-4}
-THR = {0: 1e-10, 1: 1e-5, 2: 1e-5}
-FULL_TOL = {0: 1e-9, 1: 1e-3, 2: 1e-4}   # whole-sample comparison (see above)
-NAME = {0: "fp64", 1: "split", 2: "split6"}
+TOL = {0: 1e-9, 1: 1e-4, 2: 1e-4, 3: 1e-4}
+THR = {0: 1e-10, 1: 1e-5, 2: 1e-5, 3: 1e-5}
+FULL_TOL = {0: 1e-9, 1: 1e-3, 2: 1e-4, 3: 1e-4}   # whole-sample comparison (see above)
+NAME = {0: "fp64", 1: "split", 2: "split6", 3: "fp16"}
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +64,7 @@ def _call(B, K, uts, prec, As, outs=None):
                                      outs=outs)
 
 
-@pytest.fixture(scope="module", params=[0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.fixture(scope="module", params=[0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 def run(request, setup):
     B, dev, K, Kh, us = setup
     prec = request.param
@@ -125,7 +127,7 @@ def test_rank_invariant_on_64_streams(setup):
     of eight, both precisions: |Y| = 4096 exactly and info = 0."""
     B, dev, K = setup[0], setup[1], setup[2]
     As = [torch.empty_like(K) for _ in range(BATCH)]
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 3):
         sizes, infos = [], []
         for c in range(64 // BATCH):
             uts = [torch.from_numpy(W.uniform_stream(N, seed=2000 + BATCH * c + i)).to(dev)

@@ -4,7 +4,8 @@ the same seeded inputs and uniform streams, through the C ABI.
 Tolerances (per run):
   FP64 path: pre-decision probabilities |d_gpu - d_oracle| <= 1e-9 and
              |ll_gpu - ll_oracle| <= 1e-9 |ll_oracle|; near-tie threshold 1e-10.
-  split-BF16 paths (three and six products): 1e-4 and near-tie threshold 1e-5.
+  split-BF16 paths (three and six products) and the FP16 form (real
+             Hermitian only): 1e-4 and near-tie threshold 1e-5.
   FP32 storage (FP64 updates): 1e-5, threshold 1e-6 (each stored Schur
              complement entry is rounded to FP32, relative 6e-8 per step).
 A mask difference is allowed only as a counted near tie (tests/parity.py).
@@ -34,12 +35,20 @@ def _gpu():
     yield
 
 
-TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5), 2: (1e-4, 1e-5)}
-PRECS = [0, 1, 2]
-PREC_ID = {0: "fp64", 1: "split", 2: "split6"}
+TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5), 2: (1e-4, 1e-5), 3: (1e-4, 1e-5)}
+PRECS = [0, 1, 2, 3]
+PRECS_LU = [0, 1, 2]
+PREC_ID = {0: "fp64", 1: "split", 2: "split6", 3: "fp16"}
+
+
+def _need(herm, prec):
+    if prec == 3 and not herm:
+        pytest.skip("the FP16 form serves real Hermitian problems; LU rejects it "
+                    "(test_fp16_form_rejects_lu_and_complex)")
 
 
 def _run(herm, K, u, prec, dtype=torch.float64):
+    _need(herm, prec)
     A = B.colmajor(np.asarray(K), device=DEV, dtype=dtype)
     ut = torch.from_numpy(np.ascontiguousarray(u)).to(DEV)
     fn = B.dpp_sample_ldlh if herm else B.dpp_sample_lu
@@ -72,7 +81,7 @@ def test_ldlh_small_sizes(n, prec):
     _check(True, K, u, prec)
 
 
-@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+@pytest.mark.parametrize("prec", PRECS_LU, ids=lambda p: PREC_ID[p])
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 200, 300, 513])
 def test_lu_small_sizes(n, prec):
     K, _ = W.similarity_kernel(n, seed=30 + n)
@@ -107,7 +116,7 @@ def test_ldlh_dense_kernel_n1024_streams(prec):
     assert ties <= 1
 
 
-@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+@pytest.mark.parametrize("prec", PRECS_LU, ids=lambda p: PREC_ID[p])
 def test_lu_similarity_kernel_n1024(prec):
     """K = S H S^-1 sampled by the LU path matches the oracle, and its mask
     equals the LDL^H path's on H (Prop. 2)."""
@@ -137,7 +146,7 @@ def test_fp32_storage_split():
     _check(True, K, u, 1, tol=1e-4, thr=1e-5, dtype=torch.float32)
 
 
-@pytest.mark.parametrize("prec", PRECS, ids=lambda p: PREC_ID[p])
+@pytest.mark.parametrize("prec", PRECS_LU, ids=lambda p: PREC_ID[p])
 def test_fp32_storage_lu(prec):
     """LU on an FP32-stored non-symmetric kernel (a diagonal similarity, n =
     700: ten full blocks and a ragged one) against the oracle on the same
@@ -204,6 +213,7 @@ def test_largest_leading_dimension(herm, prec):
     """lda = 2^20, the documented maximum (strips of 256 columns then span
     just under 2^31 bytes): the results match the oracle and sampled padding
     entries are untouched."""
+    _need(herm, prec)
     n, lda = 300, 1 << 20
     K = W.hermitian_kernel(n, seed=14) if herm else W.similarity_kernel(n, seed=14)[0]
     u = W.uniform_stream(n, seed=1400)
@@ -232,6 +242,7 @@ def test_largest_leading_dimension(herm, prec):
 def test_batched_equals_single_bitwise(herm, prec, ns):
     """Each problem of a batch with uneven sizes equals its single call bit for
     bit (the blocking never depends on the other sizes in the batch)."""
+    _need(herm, prec)
     Ks = [W.hermitian_kernel(n, seed=90 + n) if herm else W.similarity_kernel(n, seed=90 + n)[0]
           for n in ns]
     us = [W.uniform_stream(n, seed=9000 + n) for n in ns]
@@ -255,6 +266,7 @@ def test_out_of_place_equals_in_place(herm, prec):
     padded leading dimension on another), each A receives exactly the in-place
     factor (the lower triangle for LDL^H, whose strict upper triangle of A is
     left unwritten), the outputs match bit for bit, and K is unchanged."""
+    _need(herm, prec)
     ns = [700, 700, 1100, 129]
     Ks = [W.hermitian_kernel(n, seed=60 + i) if herm else W.similarity_kernel(n, seed=60 + i)[0]
           for i, n in enumerate(ns)]
@@ -576,3 +588,23 @@ def test_decision_diagnostics(prec):
         d = ref["predec"][:npiv]
         assert st[1] == pytest.approx(float(np.sum((d < -1e-12) | (d > 1 + 1e-12))), abs=2)
         assert 0.0 <= st[2] <= t
+
+
+def test_fp16_form_rejects_lu_and_complex():
+    """The FP16 form serves real Hermitian problems only: LU calls and complex
+    kernels with it return DPP_ERR_INVALID_ARG before any launch, leaving A
+    and the outputs unwritten."""
+    n = 200
+    K, _ = W.similarity_kernel(n, seed=180)
+    A = B.colmajor(K, device=DEV)
+    before = A.clone()
+    with pytest.raises(B.DppError) as e:
+        B.dpp_sample_lu(A, torch.from_numpy(W.uniform_stream(n, seed=18000)).to(DEV), prec=3)
+    assert e.value.status == 1
+    Z = B.colmajor(W.complex_hermitian_kernel(n, seed=181), device=DEV)
+    zb = Z.clone()
+    with pytest.raises(B.DppError) as e:
+        B.dpp_sample_ldlh(Z, torch.from_numpy(W.uniform_stream(n, seed=18001)).to(DEV), prec=3)
+    assert e.value.status == 1
+    torch.cuda.synchronize()
+    assert torch.equal(A, before) and torch.equal(Z, zb)

@@ -45,12 +45,12 @@ def cutover():
 
 
 DEV = torch.device("cuda:0") if torch.cuda.is_available() else None
-TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5), 2: (1e-4, 1e-5)}
+TOL = {0: (1e-9, 1e-10), 1: (1e-4, 1e-5), 2: (1e-4, 1e-5), 3: (1e-4, 1e-5)}
 
 
 @pytest.mark.parametrize("cut", [128, 192])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 def test_parity_on_both_sides_of_the_cutover(B, cutover, prec, dtype, cut):
     cutover(cut)
     worst = 0.0
@@ -84,7 +84,7 @@ def test_parity_on_both_sides_of_the_cutover(B, cutover, prec, dtype, cut):
     print(f"[accuracy] small path prec={prec} {dtype}: cutover {cut}, max |d - d_oracle| = {worst:.3e}")
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 def test_partial_small_problem_leaves_the_conditional_kernel(B, cutover, prec):
     cutover(192)
     for n in (65, 128, 192):
@@ -102,7 +102,7 @@ def test_partial_small_problem_leaves_the_conditional_kernel(B, cutover, prec):
         assert np.max(np.abs(got[64:, 64:][low] - S_ref[low])) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 def test_mixed_batch_equals_single_calls(B, cutover, prec):
     cut = cutover(128)
     ns = [5, cut, cut + 1, 300, 40, 1]
@@ -126,7 +126,7 @@ def test_mixed_batch_equals_single_calls(B, cutover, prec):
 def _tuned_cutover(prec):
     path = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1905_00165_amd", "csrc",
                         "tuning.h")
-    m = re.search(r"kSmallCutover\[3\] = \{([^}]*)\}", open(path).read())
+    m = re.search(r"kSmallCutover\[4\] = \{([^}]*)\}", open(path).read())
     return [int(x) for x in m.group(1).split(",")][prec]
 
 

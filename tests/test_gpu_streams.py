@@ -58,11 +58,13 @@ def _equal(a, b):
 
 
 @pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 def test_batch_of_64_equals_single_calls_and_replay(B, prec, herm):
     """The 64-problem batch equals single calls (one problem per size), and a
     graph of it captured on another stream replays that result bit for bit,
     with eager calls in between."""
+    if prec == 3 and not herm:
+        pytest.skip("the FP16 form serves real Hermitian problems")
     Ks, us, As, outs = _problems(B, seed=60, herm=herm)
     ws = torch.empty(B.dpp_workspace_size_batched(herm, B.DPP_F64, NS, prec), dtype=torch.uint8,
                      device=DEV)
@@ -120,7 +122,7 @@ def test_two_callers_streams_at_once(B):
         assert _equal(_snapshot(As, outs), ref)
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 @pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
 def test_launch_count_does_not_grow_with_size_groups(B, herm, prec):
     """All size groups of a batch share each step's launch: the batch of six
@@ -128,6 +130,8 @@ def test_launch_count_does_not_grow_with_size_groups(B, herm, prec):
     largest n alone, and at most three update launches (one per tile shape)
     where that problem issues one; Hermitian problems at or below the small
     cutover take one launch of their own."""
+    if prec == 3 and not herm:
+        pytest.skip("the FP16 form serves real Hermitian problems")
     Ks, us, As, outs = _problems(B, 11, herm)
     fb = B.dpp_sample_ldlh_batched if herm else B.dpp_sample_lu_batched
     B.dpp_profile_begin()
@@ -139,7 +143,7 @@ def test_launch_count_does_not_grow_with_size_groups(B, herm, prec):
     single = B.dpp_profile_end()
     torch.cuda.synchronize()
     leaf = "leaf_ldlh" if herm else "leaf_lu"
-    upd = {0: "update_f64", 1: "update_bf16x3", 2: "update_bf16x6"}[prec]
+    upd = {0: "update_f64", 1: "update_bf16x3", 2: "update_bf16x6", 3: "update_fp16x3"}[prec]
     print(f"[launches] {'ldlh' if herm else 'lu'} prec={prec}: batch {leaf} {batch[leaf]['launches']} "
           f"{upd} {batch[upd]['launches']}; single n={NS[big]}: {single[leaf]['launches']} "
           f"{single[upd]['launches']}")

@@ -24,7 +24,7 @@ def _outs(ns, dev):
              "stats": torch.empty(3, dtype=torch.float64, device=dev)} for n in ns]
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 def test_noalloc_equals_workspace_call(prec):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
