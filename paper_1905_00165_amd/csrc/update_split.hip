@@ -125,7 +125,7 @@ using Wide6 = Shape<128, 128, 2, 2, 2, 1, 16, 3, 3, 4>;
 using Medium6 = Wide6;
 using Narrow6 = Shape<128, 64, 4, 1, 2, 1, 32, 2, 3, 2>;
 // FP16 form: chunks of 64 k scaled into FP32 totals, as the six products.
-using Wide16 = Shape<128, 128, 2, 2, 2, 1, 16, 3, 2, 4, true>;
+using Wide16 = Shape<128, 128, 2, 2, 2, 1, 16, 4, 2, 4, true>;
 using Narrow16 = Shape<128, 64, 4, 1, 2, 1, 32, 2, 2, 2, true>;
 
 // MFMAs spread evenly over the READS fragment reads that follow the first
@@ -369,6 +369,11 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     constexpr int NSCALE = S::F16 ? S::RB + 4 * S::CB : 0;  // loads per chunk
     float rsv[S::F16 ? S::RB : 1];
     f4v csv[S::F16 ? S::CB : 1][4];
+    // Loads through the global address space: a generic (flat) load would
+    // also count against the LDS wait counter, so the fragment waits of the
+    // chunk's first stage would wait for these loads as well.
+    typedef const __attribute__((address_space(1))) float* gfloat_t;
+    typedef const __attribute__((address_space(1))) f4v* gf4v_t;
     auto load_scales = [&](int st) {
         if constexpr (S::F16) {
             const int c = (kk0 + st * S::KC) / 64;  // the chunk's 64-column block
@@ -376,7 +381,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
             for (int rb = 0; rb < S::RB; ++rb) {
                 int64_t g = rowT0 + wr * (S::TM / S::WR) + rb * 32 + (lane & 31);
                 g = g < rEnd - 1 ? g : rEnd - 1;
-                rsv[rb] = P.scale[scale_off(n, ss, 0, c, g)];
+                rsv[rb] = *(gfloat_t)(P.scale + scale_off(n, ss, 0, c, g));
             }
             const int64_t last4 = (colEnd - 1) & ~(int64_t)3;
 #pragma unroll
@@ -385,7 +390,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
                 for (int q = 0; q < 4; ++q) {
                     int64_t g = colT0 + wc * (S::TN / S::WC) + cb * 32 + 8 * q + 4 * (lane >> 5);
                     g = g < last4 ? g : last4;
-                    csv[cb][q] = *reinterpret_cast<const f4v*>(P.scale + scale_off(n, ss, 1, c, g));
+                    csv[cb][q] = *(gf4v_t)(P.scale + scale_off(n, ss, 1, c, g));
                 }
         }
     };
@@ -494,10 +499,15 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     for (int p = 0; p < S::NST - 1; ++p) issue_stage(p);
     // One stage: wait for its copies, refill the buffer freed last, then its
     // k steps on the matrix cores.
-    // first_c (std::bool_constant): the first stage of an FP16 chunk, which
+    // first_c (std::bool_constant): the first stage of a chunk of the
+    // two-level forms. Its first product term starts the chunk sums from zero
+    // (so the flush need not clear the accumulators), and in the FP16 form it
     // also loads the chunk's factors.
+    const f16v zero16 = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f,
+                         0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     auto stage = [&](int st, bool prefetch_c, auto first_c) {
-        constexpr bool LOAD_SCALES = S::F16 && decltype(first_c)::value;
+        constexpr bool FRESH = TWO_LEVEL && decltype(first_c)::value;
+        constexpr bool LOAD_SCALES = S::F16 && FRESH;
         const int buf = st % S::NST;
         // This wavefront's copies of stage st are in LDS (the NST - 2 later
         // stages already issued may still be in flight); the barrier makes
@@ -546,21 +556,26 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
         };
         // The products of one accumulator are RB*CB MFMAs apart, so
         // consecutive MFMAs never wait on each other's result.
-        auto mfmas = [&](int ks) {
+        // fresh_c (std::bool_constant): the first k step of a chunk, whose
+        // first term accumulates onto zero.
+        auto mfmas = [&](int ks, auto fresh_c) {
 #pragma unroll
             for (int term = 0; term < S::NTERM; ++term)
 #pragma unroll
                 for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
                     for (int cb = 0; cb < S::CB; ++cb) {
+                        const f16v c = (decltype(fresh_c)::value && term == 0) ? zero16 : acc[rb][cb];
                         if constexpr (S::F16)
                             acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                                wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], acc[rb][cb], 0, 0, 0);
+                                wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], c, 0, 0, 0);
                         else
                             acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], acc[rb][cb], 0, 0, 0);
+                                wp[term_b(term)][ks][cb], lp[term_a(term)][ks][rb], c, 0, 0, 0);
                     }
         };
+        constexpr auto fresh0 = std::bool_constant<FRESH>{};
+        constexpr auto later = std::false_type{};
         if constexpr (S::KSTEPS == 2) {
             if constexpr (LOAD_SCALES) load_scales(st);
             read_frags(0);
@@ -569,8 +584,8 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
             // write LDS, so they cannot move above reads of LDS; the buffer
             // they fill was last read before the barrier).
             issue_stage(st + S::NST - 1);
-            mfmas(0);
-            mfmas(1);
+            mfmas(0, fresh0);
+            mfmas(1, later);
             // Schedule: (a chunk's factors,) k step 0's fragment reads, then
             // its MFMAs with k step 1's reads interleaved evenly, then k step
             // 1's MFMAs with the next stage's copies in between.
@@ -587,7 +602,7 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
             if constexpr (LOAD_SCALES) load_scales(st);
             read_frags(0);
             issue_stage(st + S::NST - 1);  // after the fragment reads, as above
-            mfmas(0);
+            mfmas(0, fresh0);
             // Schedule: (a chunk's factors,) the fragments of the first
             // product term (p0 x p0'), then its MFMAs with the remaining
             // fragment reads interleaved, then the next stage's copies between
@@ -609,19 +624,16 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
     };
     if constexpr (TWO_LEVEL) {
         // Chunks of FL stages; after each the FP32 sums move into the FP32
-        // totals and restart from zero. The flush sits outside the
-        // stage loop, unconditionally: a flush inside it (taken on some
-        // iterations) makes the accumulators a merge of two values at the
-        // loop's back edge, which the compiler then keeps in VGPRs and copies
-        // to and from the MFMA's accumulation registers every stage.
+        // totals, and the chunk's first stage (peeled) restarts them from
+        // zero. The flush sits outside the stage loop, unconditionally: a
+        // flush inside it (taken on some iterations) makes the accumulators a
+        // merge of two values at the loop's back edge, which the compiler
+        // then keeps in VGPRs and copies to and from the MFMA's accumulation
+        // registers every stage.
         for (int s0 = 0; s0 < nstages; s0 += S::FL) {
             const int s1 = s0 + S::FL < nstages ? s0 + S::FL : nstages;
-            if constexpr (S::F16) {
-                stage(s0, false, std::true_type{});
-                for (int st = s0 + 1; st < s1; ++st) stage(st, false, std::false_type{});
-            } else {
-                for (int st = s0; st < s1; ++st) stage(st, false, std::false_type{});
-            }
+            stage(s0, false, std::true_type{});
+            for (int st = s0 + 1; st < s1; ++st) stage(st, false, std::false_type{});
 #pragma unroll
             for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
@@ -633,7 +645,6 @@ __device__ __forceinline__ void update_body(const DevProb* __restrict__ probs, c
                                                              acct[rb][cb][e]);
                         else
                             acct[rb][cb][e] += acc[rb][cb][e];
-                        acc[rb][cb][e] = 0.0f;
                     }
         }
     } else {
