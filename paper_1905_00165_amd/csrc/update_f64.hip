@@ -310,6 +310,184 @@ __global__ __launch_bounds__(256, 2) void update_f64(const DevProb* __restrict__
     }
 }
 
+// Real Hermitian kernels with FP64 storage: the same product with the operands
+// copied straight from A into LDS by the direct-to-LDS loads
+// (global_load_lds_dword), so no register staging and no LDS store phase at
+// the end of a chunk. A stage holds 16 k of both operands: k-row kk of an
+// operand is its 128 rows of column k (1 KiB), in four 256-byte blocks of 32
+// rows. One copy instruction fills one block: lane j supplies word j % 2 of
+// the double at slot j / 2, and the rows are clamped one by one (rows past
+// the region re-read the last one; they only feed accumulators that are
+// never stored). Within a block, odd k-rows hold row m at slot m ^ 16: the
+// 16 lanes of a fragment read that take k-row kk + 1 then use the other 32
+// banks from the 16 that take k-row kk. B is L unscaled; the pivots d'_k
+// multiply its fragments as they are read (the product the register path
+// forms before its LDS store, so the results are the same); they are copied
+// with the operands (32 from the stage's first k, indices clamped to n - 1),
+// so no register holds a load across stages. Two stages: the next one is
+// copied while the current one is multiplied, one barrier each.
+constexpr int kDmaOps = 2 * KC * TM * 8;   // bytes: A then B, 16 k-rows of 1 KiB each
+constexpr int kDmaStage = kDmaOps + 256;   // then the pivots
+static_assert(TM == TN, "both operands in 128-row k-rows");
+
+__global__ __launch_bounds__(256, 2) void update_f64_dma(const DevProb* __restrict__ probs, GroupMap M,
+                                                      Region rg, int64_t k0, int kw)
+{
+    typedef const void __attribute__((address_space(1)))* gptr_t;
+    typedef void __attribute__((address_space(3)))* lptr_t;
+    int pi, tw, unused;
+    if (!group_slot(M, xcd_order(blockIdx.x, gridDim.x), pi, tw, unused)) return;
+    const DevProb P = probs[pi];
+    const int64_t n = P.n;
+    const int64_t rEnd = rg.r0 + rg.rlen < n ? rg.r0 + rg.rlen : n;
+    const int64_t cEnd = rg.c0 + rg.clen < n ? rg.c0 + rg.clen : n;
+    const int64_t nrows = rEnd - rg.r0, ncols = cEnd - rg.c0;
+    if (nrows <= 0 || ncols <= 0 || k0 + kw > n || k0 >= P.npiv) return;
+    if (k0 + kw > P.npiv) kw = (int)(P.npiv - k0);
+    const int64_t NR = (nrows + TM - 1) / TM, NC = (ncols + TN - 1) / TN;
+    TileCoord tc;
+    if (!tile_of(tw, NR, NC, true, tc)) return;
+
+    double* __restrict__ A = static_cast<double*>(P.A);
+    const int64_t lda = P.lda;
+    int64_t lds_;
+    const double* __restrict__ Csrc = first_source<double>(P, k0 == 0, lds_);
+    const double* __restrict__ piv = P.piv;
+
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * kDmaStage];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t rowA0 = rg.r0 + tc.i0, colB0 = rg.c0 + tc.j0;
+
+    // Copies: wavefront w fills k-rows 4w .. 4w + 3 of both operands, four
+    // blocks each (32 copies per stage). Byte offsets in a column of A of
+    // this lane's double in block q, for even and odd k-rows (A side, B side).
+    int offA[4][2], offB[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const int m = (lane >> 1) ^ (par << 4);
+            int64_t ga = rowA0 + 32 * q + m, gb = colB0 + 32 * q + m;
+            ga = ga < rEnd - 1 ? ga : rEnd - 1;
+            gb = gb < cEnd - 1 ? gb : cEnd - 1;
+            offA[q][par] = (int)(ga * 8) + 4 * (lane & 1);
+            offB[q][par] = (int)(gb * 8) + 4 * (lane & 1);
+        }
+    const int nstages = kw / KC;
+    // Stage st's copies (past the last stage they re-read it into the buffer
+    // that is free next, so the copies stay branch-free); wavefront 0 also
+    // copies the stage's pivots.
+    auto issue_stage = [&](int st) {
+        const int64_t kc = k0 + (int64_t)(st < nstages ? st : nstages - 1) * KC;
+        unsigned char* const dst = lds + (st & 1) * kDmaStage;
+        if (wave == 0) {
+            const int64_t ip = kc + (lane >> 1) < n - 1 ? kc + (lane >> 1) : n - 1;
+            __builtin_amdgcn_global_load_lds((gptr_t)(reinterpret_cast<const char*>(piv + ip) + 4 * (lane & 1)),
+                                             (lptr_t)(dst + kDmaOps), 4, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kk = 4 * wave + r;
+            const char* col = reinterpret_cast<const char*>(A + (kc + kk) * lda);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __builtin_amdgcn_global_load_lds((gptr_t)(col + offA[q][kk & 1]),
+                                                 (lptr_t)(dst + kk * 1024 + q * 256), 4, 0, 0);
+                __builtin_amdgcn_global_load_lds((gptr_t)(col + offB[q][kk & 1]),
+                                                 (lptr_t)(dst + KC * 1024 + kk * 1024 + q * 256), 4, 0, 0);
+            }
+        }
+    };
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+
+    // Fragment slots: lane l reads row (16 b + l % 16) of its wavefront's 64
+    // rows in k-row 4 ks + l / 16; the parity of that k-row is bit 4 of l.
+    const int par = (lane >> 4) & 1;
+    int fa[4], fb[4];  // byte offsets inside a k-row
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int ra = wm * 64 + b * 16 + (lane & 15), rb = wn * 64 + b * 16 + (lane & 15);
+        fa[b] = (ra >> 5) * 256 + (((ra & 31) ^ (par << 4)) << 3) + (lane >> 4) * 1024;
+        fb[b] = (rb >> 5) * 256 + (((rb & 31) ^ (par << 4)) << 3) + (lane >> 4) * 1024;
+    }
+
+    issue_stage(0);
+    for (int st = 0; st < nstages; ++st) {
+        // This wavefront's copies and pivot loads of stage st are complete
+        // (nothing later has been issued); the barrier makes every
+        // wavefront's copies visible and retires every read of the buffer
+        // refilled next (last read in stage st - 1).
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        asm volatile("s_barrier" ::: "memory");
+        const unsigned char* const B0 = lds + (st & 1) * kDmaStage;
+        double dk[4];  // the pivot of k-row 4 ks + lane / 16
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            dk[ks] = *reinterpret_cast<const double*>(B0 + kDmaOps + (4 * ks + (lane >> 4)) * 8);
+        double af[4][4], bf[4][4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            af[0][b] = *reinterpret_cast<const double*>(B0 + fa[b]);
+            bf[0][b] = *reinterpret_cast<const double*>(B0 + KC * 1024 + fb[b]) * dk[0];
+        }
+        issue_stage(st + 1);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            if (ks + 1 < 4) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    af[ks + 1][b] = *reinterpret_cast<const double*>(B0 + (ks + 1) * 4096 + fa[b]);
+                    bf[ks + 1][b] =
+                        *reinterpret_cast<const double*>(B0 + KC * 1024 + (ks + 1) * 4096 + fb[b]) * dk[ks + 1];
+                }
+            }
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ks][bj], af[ks][bi], acc[bi][bj],
+                                                                       0, 0, 0);
+        }
+    }
+    // The copies issued past the last stage still write LDS.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+
+    // Epilogue as in update_f64 (D layout: lane l holds C row l % 16 and C
+    // columns l / 16 + 4e of each 16 x 16 block).
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+        const int64_t gr = rowA0 + wm * 64 + bi * 16 + (lane & 15);
+        double* const rowp = A + gr;
+        const double* const srcp = Csrc + gr;
+        double cv[4][4];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
+                const bool ok = gr < rEnd && gc < cEnd && gr >= gc;
+                cv[bj][e] = ok ? gload(srcp + gc * lds_) : 0.0;
+            }
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gc = colB0 + wn * 64 + bj * 16 + (lane >> 4) + 4 * e;
+                const bool ok = gr < rEnd && gc < cEnd && gr >= gc;
+                if (ok) gstore(rowp + gc * lda, cv[bj][e] - acc[bi][bj][e]);
+            }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, const GroupSpan* spans,
@@ -341,7 +519,7 @@ hipError_t launch_update_f64(bool herm, int dtype, const DevProb* probs, const G
         if (herm) hipLaunchKernelGGL((update_f64<double, true, true>), grid, block, 0, s, probs, M, rg, k0, kw);
         else hipLaunchKernelGGL((update_f64<double, false, true>), grid, block, 0, s, probs, M, rg, k0, kw);
     } else if (herm) {
-        if (dtype == 0) hipLaunchKernelGGL((update_f64<double, true, false>), grid, block, 0, s, probs, M, rg, k0, kw);
+        if (dtype == 0) hipLaunchKernelGGL(update_f64_dma, grid, block, 0, s, probs, M, rg, k0, kw);
         else hipLaunchKernelGGL((update_f64<float, true, false>), grid, block, 0, s, probs, M, rg, k0, kw);
     } else {
         if (dtype == 0) hipLaunchKernelGGL((update_f64<double, false, false>), grid, block, 0, s, probs, M, rg, k0, kw);
