@@ -480,8 +480,8 @@ def bench_complex_lu(torch, B, W, dev, cpu_seconds):
 
 def bench_lensemble(torch, B, W, dev, count=4096):
     """`count` L-ensemble marginal kernels, n_i ~ U{64..1024}, rank 64, formed in
-    FP64 and stored FP32, one sample each in one batched LDL^H call, both paths,
-    timed as a graph replay of the out-of-place call.
+    FP64 and stored FP32, one sample each in one batched LDL^H call, every
+    precision, timed as a graph replay of the out-of-place call.
     TFLOP/s counts sum n_i^3/3. Checks: every info = 0 and |Y_i| <= 64."""
     ns = W.lensemble_batch_sizes(count, seed=4)
     offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
@@ -517,8 +517,8 @@ def bench_lensemble(torch, B, W, dev, count=4096):
     infos = torch.empty(count, dtype=torch.int32, device=dev)
     outs = [{"mask": mflat[int(uoffs[i]):int(uoffs[i + 1])], "pivots": pflat[int(uoffs[i]):int(uoffs[i + 1])],
              "loglik": lls[i:i + 1], "info": infos[i:i + 1]} for i in range(count)]
-    for name, prec in (("split6", B.DPP_PREC_SPLIT_BF16X6), ("split", B.DPP_PREC_SPLIT_BF16),
-                       ("fp64", B.DPP_PREC_FP64)):
+    for name, prec in (("split6", B.DPP_PREC_SPLIT_BF16X6), ("fp16", B.DPP_PREC_SPLIT_FP16),
+                       ("split", B.DPP_PREC_SPLIT_BF16), ("fp64", B.DPP_PREC_FP64)):
         ws = torch.empty(B.dpp_workspace_size_batched(True, B.DPP_F32, [int(x) for x in ns], prec),
                          dtype=torch.uint8, device=dev)
 

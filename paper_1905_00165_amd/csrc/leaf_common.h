@@ -220,6 +220,10 @@ __device__ __forceinline__ void store_pieces8(uint16_t* base, int64_t n, int ss,
 // FP16 form: hi = fp16(y), lo = fp16(y - hi) of 8 consecutive (already
 // scaled) values y[0..7] of row r, columns kk .. kk+7 of the outer panel;
 // piece i goes to the plane at first + i * stride, one 16-byte store each.
+// Both conversions go through FP32 (the hardware conversions; a direct FP64
+// to FP16 conversion is a long software sequence): hi may then differ from
+// the correctly rounded fp16(y) by one unit in rare cases, which the exact
+// remainder y - hi absorbs, so the pair still carries about 22 bits of y.
 __device__ __forceinline__ void store_f16_pieces8_at(uint16_t* first, int64_t stride, int ss,
                                                      int64_t r, int kk, const double (&y)[8])
 {
@@ -230,8 +234,14 @@ __device__ __forceinline__ void store_f16_pieces8_at(uint16_t* first, int64_t st
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const double v = y[2 * p2 + t];
-            const _Float16 hi = (_Float16)v;
-            const _Float16 lo = (_Float16)(v - (double)hi);
+            // The empty asm keeps the code generator from merging the two
+            // conversions back into one FP64 -> FP16 rounding.
+            float vf = (float)v;
+            asm volatile("" : "+v"(vf));
+            const _Float16 hi = (_Float16)vf;
+            float rf = (float)(v - (double)hi);
+            asm volatile("" : "+v"(rf));
+            const _Float16 lo = (_Float16)rf;
             h[t] = __builtin_bit_cast(uint16_t, hi);
             l[t] = __builtin_bit_cast(uint16_t, lo);
         }
@@ -245,15 +255,16 @@ __device__ __forceinline__ void store_f16_pieces8_at(uint16_t* first, int64_t st
 }
 
 // The FP16 form's column balance rho = 2^h, h = floor(x / 2) for |d'| in
-// [2^(x-1), 2^x) (about sqrt|d'|; 1 for d' = 0), so that l rho = (w / d') rho
-// and w / rho are both near |w| / sqrt|d'|; and the exponent e that brings a
-// row block's largest magnitude m into (2^13, 2^14] (0 for m = 0).
-__device__ __forceinline__ double f16_rho(double d)
+// [2^(x-1), 2^x) (about sqrt|d'|; h = 0 for d' = 0), so that l rho =
+// (w / d') rho and w / rho are both near |w| / sqrt|d'| (returned: h, so that
+// both scalings are exponent shifts); and the exponent e that brings a row
+// block's largest magnitude m into (2^13, 2^14] (0 for m = 0).
+__device__ __forceinline__ int f16_rho_exp(double d)
 {
-    if (d == 0.0) return 1.0;
+    if (d == 0.0) return 0;
     int x;
     (void)__builtin_frexp(d, &x);
-    return __builtin_ldexp(1.0, x >> 1);
+    return x >> 1;
 }
 __device__ __forceinline__ int f16_row_exp(double m)
 {

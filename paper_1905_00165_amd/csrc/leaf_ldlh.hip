@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
     __shared__ __attribute__((aligned(16))) double smem[kSmem];
     double* const sB = smem;               // chain: broadcast columns of the current two pivots
     double* const sR = smem + L;           // 1 / D1 (written after the chain, over sB's second half)
-    double* const sRho = smem;             // F16: column balance (after the chain, sB's first half)
+    int* const sRho = reinterpret_cast<int*>(smem);  // F16: column balance exponents (after the chain, over sB)
     double* const sL = smem + 2 * L;       // sL[t*kBP + k] = L11[k][t] for k > t, zero elsewhere
     double* const sI = sL + L * kBP;       // the inverses of L11's 16 x 16 diagonal blocks
     double* const sT = sI + 4 * kInvBlock;  // per wavefront: W of one row group, row-major
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
 #pragma unroll
         for (int k = 0; k < L; ++k) sL[k * kBP + lane] = (k < lane && lane < bs) ? a[k] : 0.0;
         sR[lane] = (lane < bs) ? 1.0 / mydp : 1.0;
-        if constexpr (F16) sRho[lane] = (lane < bs) ? f16_rho(mydp) : 1.0;
+        if constexpr (F16) sRho[lane] = (lane < bs) ? f16_rho_exp(mydp) : 0;
 
         // The factored block goes to the workspace strip, not to A: other
         // workgroups of this launch may still be loading the original block
@@ -231,9 +231,10 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_ldlh(const DevProb* __restri
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
                         const int col = 32 * half + tc + c;
-                        const double w = tile[tr * kTilePitch + col], rho = sRho[col];
-                        wv[half][c] = w / rho;                // W / rho (exact: a power of two)
-                        lv[half][c] = w * sR[col] * rho;      // L rho
+                        const double w = tile[tr * kTilePitch + col];
+                        const int h = sRho[col];
+                        wv[half][c] = __builtin_ldexp(w, -h);            // W / rho
+                        lv[half][c] = __builtin_ldexp(w * sR[col], h);   // L rho
                         mw = __builtin_fmax(mw, __builtin_fabs(wv[half][c]));
                         ml = __builtin_fmax(ml, __builtin_fabs(lv[half][c]));
                     }
