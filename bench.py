@@ -599,7 +599,7 @@ def bench_lensemble(torch, B, W, dev, count=4096):
     return out
 
 
-def bench_serve(torch, B, W, dev, n_req=2000, n_sat=600):
+def bench_serve(torch, B, W, dev, n_req=20000, n_sat=600):
     """Serving loop (paper_1905_00165_amd/serve.py) over 256 resident L-ensemble
     kernels, rank 64, FP32 storage, n ~ round(LogNormal(ln 1024, 0.75)) clipped to
     [128, 8192]. Requests pick a kernel uniformly and carry their own stream.
