@@ -603,9 +603,10 @@ def bench_serve(torch, B, W, dev, n_req=20000, n_sat=600):
     """Serving loop (paper_1905_00165_amd/serve.py) over 256 resident L-ensemble
     kernels, rank 64, FP32 storage, n ~ round(LogNormal(ln 1024, 0.75)) clipped to
     [128, 8192]. Requests pick a kernel uniformly and carry their own stream.
-    The saturated FP64 rate is measured first (all of `n_sat` requests waiting
-    at t = 0); then Poisson arrivals at 0.7 x that rate, the same for both
-    paths, over `n_req` requests; samples/s and p50/p99 latency per path."""
+    After an untimed warm-up pass per path, the saturated FP64 rate is
+    measured (all of `n_sat` requests waiting at t = 0); then Poisson arrivals
+    at 0.7 x that rate, the same for both paths, over `n_req` requests;
+    samples/s and p50/p99 latency per path."""
     from paper_1905_00165_amd import serve
     rng = np.random.default_rng(5)
     ns = np.clip(np.round(rng.lognormal(np.log(1024.0), 0.75, size=256)), 128, 8192).astype(int)
@@ -624,6 +625,12 @@ def bench_serve(torch, B, W, dev, n_req=20000, n_sat=600):
         return [serve.Request(rid=i, kernel=int(kid[i]), u=us[i], arrival=float(times[i]))
                 for i in range(count)]
 
+    # One untimed pass per path first: the caching allocator's first device
+    # allocations (factor buffers and workspaces of every size) would
+    # otherwise land in the saturation measurement, which sets the rate.
+    for prec in (B.DPP_PREC_FP64, B.DPP_PREC_SPLIT_BF16):
+        serve.Server(kernels, prec=prec, **cfg).run(reqs(np.zeros(n_sat), n_sat))
+        torch.cuda.synchronize()
     saturated = {}
     for name, prec in (("fp64", B.DPP_PREC_FP64), ("split", B.DPP_PREC_SPLIT_BF16)):
         sat = serve.Server(kernels, prec=prec, **cfg)

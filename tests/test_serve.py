@@ -34,7 +34,7 @@ def test_admit_is_first_come_first_served():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "split", "split6"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "split", "split6", "fp16"])
 def test_served_results_equal_standalone_and_overlap(prec):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -54,7 +54,10 @@ def test_served_results_equal_standalone_and_overlap(prec):
     before = [K.clone() for K in kernels]
     torch.cuda.synchronize()
     srv = serve.Server(kernels, prec=prec, slots=3, mem_budget=1 << 30, max_batch=6)
+    import gc
+    collecting = gc.isenabled()
     srv.run(reqs)
+    assert gc.isenabled() == collecting   # the loop restores the collector's state
     torch.cuda.synchronize()
     assert srv.batches > 3 and srv.max_inflight >= 2
     assert all(torch.equal(K, K0) for K, K0 in zip(kernels, before))  # resident kernels only read
