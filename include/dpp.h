@@ -235,8 +235,8 @@ size_t dpp_workspace_size_batched(int hermitian, dpp_dtype dt, const int64_t* ns
  *   Returns DPP_ERR_WORKSPACE when the batch needs more than
  *   DPP_NOALLOC_SCRATCH_BYTES, i.e. when dpp_workspace_size_batched(1, dt,
  *   ns, count, prec) exceeds it (one problem fits up to n = 131008 on the
- *   FP64 path, n = 2848 with DPP_PREC_SPLIT_BF16 and n = 2304 with
- *   DPP_PREC_SPLIT_BF16X6).
+ *   FP64 path, n = 2848 with DPP_PREC_SPLIT_BF16, n = 2304 with
+ *   DPP_PREC_SPLIT_BF16X6 and n = 2816 with DPP_PREC_SPLIT_FP16).
  *   Every call on one device shares that device's scratch, which keeps the
  *   last call's contents (no call needs it zeroed): calls that may overlap on
  *   one device (different streams, or different host threads without
