@@ -241,6 +241,12 @@ def test_noalloc_argument_errors_return_before_any_launch():
     big = (B.dpp_problem * 1)(B.dpp_problem(p, 3072, 3072, p, p, p, p, p, None, 0, 0, None))
     assert B.dpp_workspace_size(True, B.DPP_F64, 3072, 2) > B.DPP_NOALLOC_SCRATCH_BYTES
     assert f(big, 1, 0, 2, None) == 2                  # DPP_ERR_WORKSPACE
+    # the largest single problems the header states for each precision
+    cap = B.DPP_NOALLOC_SCRATCH_BYTES
+    for prec, nmax in ((0, 131008), (1, 2848), (2, 2304), (3, 2816)):
+        assert 0 < B.dpp_workspace_size_batched(True, B.DPP_F64, [nmax], prec) <= cap, prec
+        assert B.dpp_workspace_size_batched(True, B.DPP_F64, [nmax + 1], prec) > cap, prec
+    assert f(big, 1, 0, 4, None) == 1                  # precision 4 is not defined
 
 
 def test_complex_workspace_and_arguments():
