@@ -659,7 +659,7 @@ def bench_serve(torch, B, W, dev, n_req=20000, n_sat=600):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (the sampler needs no second one); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

@@ -26,7 +26,7 @@ library). Workloads:
     (six products) 2048 / 4096 and FP64 1024 / 2048; LU on the similarity
     kernel n = 8192 (8 samples), 256 / 512 / 1024.
 
-Usage (on the GPU machine, after a regular build):
+Usage (on an MI355X, after a regular build):
     python -m paper_1905_00165_amd.autotune [--write] [--quick]
 Without --write the chosen values are printed only.
 """

@@ -5,7 +5,7 @@ the first differing index k has |u_k - d_k| below a threshold (d_k the
 oracle's pre-decision probability): such runs are counted as near ties (a
 rounding-level difference in d_k decided a comparison that was within rounding
 of a tie). Later differences follow from the diverged histories and are not
-judged. Pre-decision probabilities are compared up to and including k.
+compared. Pre-decision probabilities are compared up to and including k.
 """
 from dataclasses import dataclass
 
@@ -13,7 +13,7 @@ import numpy as np
 
 
 @dataclass
-class Verdict:
+class ParityResult:
     ok: bool
     near_tie: bool
     first_diff: int       # -1 if masks are identical
@@ -23,7 +23,7 @@ class Verdict:
     why: str = ""
 
 
-def compare(gpu_mask, gpu_piv, gpu_ll, ora, u, tol, thr) -> Verdict:
+def compare(gpu_mask, gpu_piv, gpu_ll, ora, u, tol, thr) -> ParityResult:
     gm = np.asarray(gpu_mask).astype(np.uint8)
     om = np.asarray(ora["mask"]).astype(np.uint8)
     n = om.shape[0]
@@ -37,7 +37,7 @@ def compare(gpu_mask, gpu_piv, gpu_ll, ora, u, tol, thr) -> Verdict:
         ll_o = ora["loglik"]
         ll_rel = abs(gpu_ll - ll_o) / max(abs(ll_o), 1e-300)
         ok = dd <= tol and ll_rel <= tol
-        return Verdict(ok, False, -1, dd, ll_rel, gap,
+        return ParityResult(ok, False, -1, dd, ll_rel, gap,
                        "" if ok else f"max|dd|={dd:.3g} ll_rel={ll_rel:.3g} > tol={tol:g}")
     k = int(diff[0])
     dd = float(np.max(np.abs(d_g[:k + 1] - d_o[:k + 1])))
@@ -45,4 +45,4 @@ def compare(gpu_mask, gpu_piv, gpu_ll, ora, u, tol, thr) -> Verdict:
     ok = tie and dd <= tol
     why = "" if ok else (f"mask differs at {k}: |u-d|={abs(u[k] - d_o[k]):.3g} >= thr={thr:g}"
                          if not tie else f"max|dd|={dd:.3g} > tol={tol:g}")
-    return Verdict(ok, tie, k, dd, float("nan"), gap, why)
+    return ParityResult(ok, tie, k, dd, float("nan"), gap, why)
