@@ -90,19 +90,27 @@ inline int groups_per_wave(int64_t rows, int nprob, int per_cu, int* gx)
 
 // Group map of one diagonal-block launch at column c0 (block width bw): for
 // each size group that has the block, its workgroups per problem and row
-// groups per wavefront (groups_per_wave, sized as if the group ran alone).
-// Returns the launch's workgroups (0: no group has the block).
+// groups per wavefront (groups_per_wave, with the rounds counted over every
+// problem of the launch: the groups share the GPU, and each extra workgroup
+// of a problem repeats its chain). Only the launch geometry depends on the
+// batch; every workgroup of a problem computes the same chain and the rows
+// are independent, so results do not. Returns the launch's workgroups (0: no
+// group has the block).
 inline int64_t leaf_map(const GroupSpan* spans, int nspan, int64_t c0, int bw, int per_cu,
                         GroupMap& M)
 {
     M.ng = 0;
     M.off[0] = 0;
     int64_t off = 0;
+    int64_t active = 0;  // problems of the launch that have this block
+    for (int i = 0; i < nspan && i < kMaxGroupsPerLaunch; ++i)
+        if (c0 < spans[i].nmax) active += spans[i].count;
+    const int nprob = (int)(active < (int64_t)1 << 30 ? active : (int64_t)1 << 30);
     for (int i = 0; i < nspan && M.ng < kMaxGroupsPerLaunch; ++i) {
         const GroupSpan& g = spans[i];
         if (c0 >= g.nmax) continue;
         int gx = 1;
-        const int gpw = groups_per_wave(g.nmax - c0 - bw, (int)g.count, per_cu, &gx);
+        const int gpw = groups_per_wave(g.nmax - c0 - bw, nprob, per_cu, &gx);
         M.p0[M.ng] = (int)g.p0;
         M.wpp[M.ng] = gx;
         M.aux[M.ng] = gpw;
