@@ -23,7 +23,7 @@ library). Workloads:
   - size groups: the 4096-kernel L-ensemble batch (n ~ U{64..1024}, FP32),
     narrow widths 64 / 128 / 256, split and FP64;
   - panel widths: LDL^H on the projection kernel n = 16384 (8 samples), split
-    (six products) 2048 / 4096 and FP64 1024 / 2048; LU on the similarity
+    (six products) 2048 / 4096 and FP64 1024 / 2048 / 4096; LU on the similarity
     kernel n = 8192 (8 samples), 256 / 512 / 1024.
 
 Usage (on an MI355X, after a regular build):
@@ -46,7 +46,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 TUNING = os.path.join(CSRC, "tuning.h")
 
-DEFAULTS = {"kB0LdlhSplit": 4096, "kB0LdlhFp64": 2048, "kB0Lu": 512, "kGroupNarrow": 128,
+DEFAULTS = {"kB0LdlhSplit": 4096, "kB0LdlhFp64": 4096, "kB0Lu": 512, "kGroupNarrow": 128,
             "kGroupSplitN": 2048, "kGroupWide": 1024, "kSmallCutover": [128, 128, 128, 128]}
 
 
@@ -276,7 +276,7 @@ def main():
         chosen["kGroupNarrow"] = best[1]
         record.append(f"  -> kGroupNarrow = {best[1]}")
         for key, task, cands, prec in (("kB0LdlhSplit", "b0_ldlh_split", (2048, 4096), 2),
-                                       ("kB0LdlhFp64", "b0_ldlh_fp64", (1024, 2048), 0),
+                                       ("kB0LdlhFp64", "b0_ldlh_fp64", (1024, 2048, 4096), 0),
                                        ("kB0Lu", "b0_lu", (256, 512, 1024), None)):
             best = None
             for c in cands:

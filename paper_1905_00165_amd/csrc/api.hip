@@ -4,7 +4,7 @@
 // Launch sequence (blocked right-looking sampler, Sec. 3; the unblocked
 // sampler of Sec. 2 on each 64-wide diagonal block):
 //
-//   LDL^H, outer block width B0 (FP64: 2048, split-BF16: 4096):
+//   LDL^H, outer block width B0 (tuning.h: 4096 for FP64 and split updates):
 //     for each outer panel [j0, j1 = j0 + B0):
 //       factor_panel(j0, B0)                       -- recursive, below
 //       update rows/cols [j1, n) by columns [j0, j1) -- the trailing update

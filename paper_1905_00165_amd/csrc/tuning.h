@@ -4,27 +4,28 @@
 // the GPU and writes this file; its record of the measurements is the comment
 // block below.
 // Record of the autotune run of 2026-12-03 (ms per call, by precision 0 = FP64,
-// 1 = split x3, 2 = split x6):
-//   1024 kernels of n = 32: small path {0: 0.0995, 1: 0.0992, 2: 0.0993}, blocked {0: 0.0923, 1: 0.0921, 2: 0.0918}
-//   1024 kernels of n = 64: small path {0: 0.1315, 1: 0.1313, 2: 0.1313}, blocked {0: 0.1119, 1: 0.1116, 2: 0.1103}
-//   1024 kernels of n = 96: small path {0: 0.1946, 1: 0.1944, 2: 0.1947}, blocked {0: 0.2187, 1: 0.1895, 2: 0.2141}
-//   1024 kernels of n = 128: small path {0: 0.3889, 1: 0.3879, 2: 0.3906}, blocked {0: 0.2468, 1: 0.2252, 2: 0.2731}
-//   1024 kernels of n = 160: small path {0: 0.4665, 1: 0.4657, 2: 0.4672}, blocked {0: 0.4183, 1: 0.3641, 2: 0.4441}
-//   1024 kernels of n = 192: small path {0: 0.8093, 1: 0.8094, 2: 0.8083}, blocked {0: 0.4967, 1: 0.4289, 2: 0.5211}
-//   -> kSmallCutover = [0, 0, 0]
-//   4096 L-ensembles, group width 64: {0: 24.8878, 2: 26.3323}
-//   4096 L-ensembles, group width 128: {0: 25.5257, 2: 26.9409}
-//   4096 L-ensembles, group width 256: {0: 29.2082, 2: 28.3778}
+// 1 = split x3, 2 = split x6, 3 = FP16 split):
+//   1024 kernels of n = 32: small path {0: 0.103, 1: 0.1028, 2: 0.103, 3: 0.1032}, blocked {0: 0.095, 1: 0.0954, 2: 0.0959, 3: 0.0958}
+//   1024 kernels of n = 64: small path {0: 0.1345, 1: 0.1344, 2: 0.1342, 3: 0.1341}, blocked {0: 0.1163, 1: 0.1156, 2: 0.1147, 3: 0.1147}
+//   1024 kernels of n = 96: small path {0: 0.2029, 1: 0.2008, 2: 0.2004, 3: 0.1998}, blocked {0: 0.2206, 1: 0.1963, 2: 0.1994, 3: 0.1963}
+//   1024 kernels of n = 128: small path {0: 0.3957, 1: 0.3944, 2: 0.3926, 3: 0.3941}, blocked {0: 0.2476, 1: 0.2238, 2: 0.2409, 3: 0.2255}
+//   1024 kernels of n = 160: small path {0: 0.4735, 1: 0.4759, 2: 0.4739, 3: 0.4762}, blocked {0: 0.4196, 1: 0.3689, 2: 0.3871, 3: 0.3712}
+//   1024 kernels of n = 192: small path {0: 0.8183, 1: 0.8187, 2: 0.818, 3: 0.818}, blocked {0: 0.5001, 1: 0.4285, 2: 0.4501, 3: 0.4319}
+//   -> kSmallCutover = [0, 0, 0, 0]
+//   4096 L-ensembles, group width 64: {0: 24.4684, 2: 18.8064}
+//   4096 L-ensembles, group width 128: {0: 25.6612, 2: 19.695}
+//   4096 L-ensembles, group width 256: {0: 29.1797, 2: 20.371}
 //   -> kGroupNarrow = 64
-//   b0_ldlh_split kB0LdlhSplit = 2048: {2: 124.3441}
-//   b0_ldlh_split kB0LdlhSplit = 4096: {2: 122.9148}
+//   b0_ldlh_split kB0LdlhSplit = 2048: {2: 82.4463}
+//   b0_ldlh_split kB0LdlhSplit = 4096: {2: 80.7221}
 //   -> kB0LdlhSplit = 4096
-//   b0_ldlh_fp64 kB0LdlhFp64 = 1024: {0: 238.8056}
-//   b0_ldlh_fp64 kB0LdlhFp64 = 2048: {0: 234.216}
-//   -> kB0LdlhFp64 = 2048
-//   b0_lu kB0Lu = 256: {0: 71.7892, 2: 49.947}
-//   b0_lu kB0Lu = 512: {0: 69.4705, 2: 46.9873}
-//   b0_lu kB0Lu = 1024: {0: 73.62, 2: 50.1623}
+//   b0_ldlh_fp64 kB0LdlhFp64 = 1024: {0: 217.4429}
+//   b0_ldlh_fp64 kB0LdlhFp64 = 2048: {0: 212.4692}
+//   b0_ldlh_fp64 kB0LdlhFp64 = 4096: {0: 210.3904}
+//   -> kB0LdlhFp64 = 4096
+//   b0_lu kB0Lu = 256: {0: 71.8761, 2: 37.8041}
+//   b0_lu kB0Lu = 512: {0: 69.6748, 2: 34.6524}
+//   b0_lu kB0Lu = 1024: {0: 73.3292, 2: 38.1667}
 //   -> kB0Lu = 512
 #pragma once
 #include <stdint.h>
@@ -35,7 +36,7 @@ namespace tuned {
 // Outer panel width of real kernels (complex kernels: half as many complex
 // columns): the trailing update re-reads the trailing matrix once per panel.
 constexpr int kB0LdlhSplit = 4096;  // Hermitian, split-BF16 updates
-constexpr int kB0LdlhFp64 = 2048;   // Hermitian, FP64 updates
+constexpr int kB0LdlhFp64 = 4096;   // Hermitian, FP64 updates
 constexpr int kB0Lu = 512;          // LU
 
 // Size groups of a batch: widths of kGroupNarrow up to n = kGroupSplitN,

@@ -202,7 +202,7 @@ def test_factor_reconstructs_sampled_entries(run, setup):
 def test_conditional_probability_deep_in_the_factorization(run, setup, j):
     """d_j from the GPU equals P[j in Y | the GPU's decisions for 0..j-1],
     the Schur complement of Props. 3-5 evaluated with a library solve; j
-    covers every 4096- (split) and 2048-column (FP64) outer panel."""
+    covers every 4096-column outer panel."""
     prec, res = run
     Kh = setup[3]
     r = res[1]

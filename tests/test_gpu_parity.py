@@ -489,7 +489,7 @@ _BIG = {}
 
 
 def _big_kernel(which):
-    """Kernels past the first outer panel (split: 4096 columns, FP64: 2048):
+    """Kernels past the first outer panel (4096 columns on both paths):
     a projection kernel n = 6144 of rank 1536 and a dense Hermitian kernel
     n = 8192, generated on the device; host copies for the oracle."""
     if which not in _BIG:
