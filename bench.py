@@ -69,6 +69,9 @@ def parse():
     p.add_argument("--extra", type=int, default=1,
                    help="also measure the other workloads (n=1024 single sample, LU n=8192, "
                         "batched L-ensembles); 0 skips them")
+    p.add_argument("--leg", choices=["plain", "lu", "complex", "lensemble", "serve"], default=None,
+                   help="measure only this other workload and print its JSON object (for "
+                        "profiling one workload); the headline line is not produced")
     return p.parse_args()
 
 
@@ -667,6 +670,16 @@ def main():
     from paper_1905_00165_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.leg:
+        cpu = min(args.cpu_seconds, 10.0)
+        legs = {"plain": lambda: bench_plain(torch, B, W, dev, args.cpu_seconds > 0),
+                "lu": lambda: bench_lu(torch, B, W, dev, cpu),
+                "complex": lambda: bench_complex_lu(torch, B, W, dev, cpu),
+                "lensemble": lambda: bench_lensemble(torch, B, W, dev),
+                "serve": lambda: bench_serve(torch, B, W, dev)}
+        log(f"[bench] {args.leg} only")
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
+        return
     n, r, bsz = args.n, args.rank, args.batch
     if args.k_cache and os.path.exists(args.k_cache):
         log(f"[bench] loading K from {args.k_cache}")
