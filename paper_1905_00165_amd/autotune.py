@@ -46,7 +46,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 TUNING = os.path.join(CSRC, "tuning.h")
 
-DEFAULTS = {"kB0LdlhSplit": 4096, "kB0LdlhFp64": 4096, "kB0Lu": 512, "kGroupNarrow": 128,
+DEFAULTS = {"kB0LdlhSplit": 4096, "kB0LdlhFp64": 4096, "kB0Lu": 2048, "kGroupNarrow": 128,
             "kGroupSplitN": 2048, "kGroupWide": 1024, "kSmallCutover": [128, 128, 128, 128]}
 
 
@@ -277,7 +277,7 @@ def main():
         record.append(f"  -> kGroupNarrow = {best[1]}")
         for key, task, cands, prec in (("kB0LdlhSplit", "b0_ldlh_split", (2048, 4096), 2),
                                        ("kB0LdlhFp64", "b0_ldlh_fp64", (1024, 2048, 4096), 0),
-                                       ("kB0Lu", "b0_lu", (256, 512, 1024), None)):
+                                       ("kB0Lu", "b0_lu", (512, 1024, 2048, 4096), None)):
             best = None
             for c in cands:
                 ms = measure(dict(chosen, **{key: c}), task, 0, log)

@@ -12,11 +12,12 @@
 //       launch; else with mid = c0 + w/2: factor_panel(c0, w/2),
 //       update rows [mid, n) x cols [mid, mid + w/2) by columns [c0, mid),
 //       factor_panel(mid, w/2). Nodes at or past the largest n are skipped.
-//   LU, outer block width B0 = 512: for each outer panel [j0, j1), 64 columns
-//     at a time: diagonal block + both panel solves (L below, U out to n),
-//     then rank-64 updates of rows [x, n) x cols [x, j1) and rows [x, j1) x
-//     cols [j1, n), x = c0 + 64; after the panel the trailing update of
-//     [j1, n) x [j1, n) by its B0 columns.
+//   LU, outer block width B0 (tuning.h): for each outer panel [j0, j1),
+//     lu_panel(j0, B0), the same binary tree: w = 64 -> one diagonal-block
+//     launch (pivots, L below, U out to n); else factor the left half, update
+//     rows [mid, n) x cols [mid, c0 + w) and rows [mid, c0 + w) x cols
+//     [c0 + w, n) by columns [c0, mid), factor the right half. After the panel
+//     the trailing update of [j1, n) x [j1, n) by its B0 columns.
 //   Then one finalize launch (loglik, info).
 //
 // Every grouping of the Schur updates is exact in exact arithmetic: the -1 of
@@ -62,9 +63,8 @@ Plan make_plan(bool herm, dpp_dtype dt, dpp_precision prec, int64_t nmax)
     // Outer panel width: each trailing update reads and writes the trailing
     // matrix once, so its HBM traffic per sample is ~ 8 n^3 / (3 B0) bytes for
     // FP64 storage; the split path needs the wider panel to stay MFMA-bound.
-    // LU's rank-64 steps inside a panel touch ~ (n - j0) B0 / 2 entries of the
-    // panel and ~ (n - j1) B0 / 2 of the rows of U to its right, against
-    // (n - j1)^2 per trailing update; B0 = 512 balances them at n = 8192.
+    // Inside a panel the binary tree passes over the panel's rows (and, for
+    // LU, its rows of U to the right) once per level, log2(B0 / 64) times.
     // A complex column is two real columns of the products' real forms, so
     // complex panels are half as wide for the same real panel width.
     if (herm) p.B0 = p.pieces ? dpp::tuned::kB0LdlhSplit : dpp::tuned::kB0LdlhFp64;
@@ -314,30 +314,31 @@ dpp_status factor_panel(const Ctx& c, int64_t c0, int64_t w, int64_t j0)
     return factor_panel(c, mid, h, j0);
 }
 
-// LU outer panel [j0, j0 + B0): 64 columns at a time. After each diagonal
-// block (which decides its pivots and solves its rows of L below it and its
-// rows of U out to column n), two rank-64 updates bring the rest of the panel
-// and the rows of U to its right up to date: rows [x, n) x columns [x, j1)
-// and rows [x, j1) x columns [j1, n), x = c0 + 64. The trailing block
+// LU columns [c0, c0 + w) of the outer panel starting at j0, w = leaf * 2^k:
+// the same fixed binary tree as factor_panel. After the left half [c0, mid)
+// is factored, its columns update, with k in [c0, mid), rows [mid, n) x
+// columns [mid, c0 + w) (the right half's diagonal block, its rows of L, and
+// its rows of U inside the node) and rows [mid, c0 + w) x columns
+// [c0 + w, n) (the right half's rows of U past the node). A diagonal block at
+// row block r then sees every k < r of the panel: the one node whose left
+// half holds k and right half holds r applied it, and each of its launches
+// solves its rows of L below it and its rows of U out to column n. The block
 // [j1, n) x [j1, n) waits for one update with K = B0 after the panel.
-dpp_status lu_panel(const Ctx& c, int64_t j0)
+dpp_status lu_panel(const Ctx& c, int64_t c0, int64_t w, int64_t j0)
 {
-    const int64_t j1 = j0 + c.plan.B0;
+    if (c0 >= c.pmax) return DPP_OK;
+    if (w <= c.plan.leaf) return leaf(c, c0, j0);
     constexpr int64_t kAll = (int64_t)1 << 62;
-    const int lw = c.plan.leaf;
-    for (int64_t c0 = j0; c0 < j1 && c0 < c.pmax; c0 += lw) {
-        dpp_status st = leaf(c, c0, j0);
+    const int64_t h = w / 2, mid = c0 + h;
+    dpp_status st = lu_panel(c, c0, h, j0);
+    if (st != DPP_OK || mid >= c.nmax) return st;
+    st = update(c, dpp::Region{mid, kAll, mid, h}, c0, (int)h, j0);
+    if (st != DPP_OK) return st;
+    if (c0 + w < c.nmax) {
+        st = update(c, dpp::Region{mid, h, c0 + w, kAll}, c0, (int)h, j0);
         if (st != DPP_OK) return st;
-        const int64_t x = c0 + lw;
-        if (x >= j1 || x >= c.nmax) continue;
-        st = update(c, dpp::Region{x, kAll, x, j1 - x}, c0, lw, j0);
-        if (st != DPP_OK) return st;
-        if (j1 < c.nmax) {
-            st = update(c, dpp::Region{x, j1 - x, j1, kAll}, c0, lw, j0);
-            if (st != DPP_OK) return st;
-        }
     }
-    return DPP_OK;
+    return lu_panel(c, mid, h, j0);
 }
 
 // Largest n of the small-problem path: the tuned cutover of the precision,
@@ -369,7 +370,7 @@ dpp_status run_groups(const Ctx& c)
     const Plan& plan = c.plan;
     for (int64_t j0 = 0; j0 < c.pmax; j0 += plan.B0) {
         const int64_t j1 = j0 + plan.B0;
-        dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : lu_panel(c, j0);
+        dpp_status st = plan.herm ? factor_panel(c, j0, plan.B0, j0) : lu_panel(c, j0, plan.B0, j0);
         if (st != DPP_OK) return st;
         if (j1 < c.nmax) {
             st = update(c, dpp::trailing_region(j1, c.nmax - j1), j0, plan.B0, j0);

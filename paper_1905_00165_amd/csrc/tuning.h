@@ -27,6 +27,12 @@
 //   b0_lu kB0Lu = 512: {0: 69.6748, 2: 34.6524}
 //   b0_lu kB0Lu = 1024: {0: 73.3292, 2: 38.1667}
 //   -> kB0Lu = 512
+// LU outer panels as a binary tree (the same blocking as LDL^H), measured on
+// the LU n = 8192 leg of the bench (32 samples; samples/s, split x3 / FP64):
+//   kB0Lu = 512: 308.8 / 118.1 (64 columns at a time before: 267.5 / 113.9)
+//   kB0Lu = 1024: 337.7 / 120.1
+//   kB0Lu = 2048: 350.5 / 123.5
+//   -> kB0Lu = 2048
 #pragma once
 #include <stdint.h>
 
@@ -37,7 +43,7 @@ namespace tuned {
 // columns): the trailing update re-reads the trailing matrix once per panel.
 constexpr int kB0LdlhSplit = 4096;  // Hermitian, split-BF16 updates
 constexpr int kB0LdlhFp64 = 4096;   // Hermitian, FP64 updates
-constexpr int kB0Lu = 512;          // LU
+constexpr int kB0Lu = 2048;         // LU
 
 // Size groups of a batch: widths of kGroupNarrow up to n = kGroupSplitN,
 // then of kGroupWide (the blocking never depends on them, only the launches).
