@@ -132,9 +132,9 @@ def test_complex_factor_reconstructs(B, prec):
 @pytest.mark.parametrize("herm", [True, False], ids=["ldlh", "lu"])
 def test_complex_past_the_outer_panel(B, herm, prec):
     """Sizes whose later pivots depend on trailing updates of a full outer
-    panel (complex panels: 2048 (split) / 1024 (FP64) columns for LDL^H, 256
+    panel (complex panels: 2048 (split) / 1024 (FP64) columns for LDL^H, 1024
     for LU), against whole oracle runs."""
-    n = 2600 if herm else 700
+    n = 2600 if herm else 1100
     K = W.complex_hermitian_kernel(n, seed=350) if herm else W.complex_similarity_kernel(n, seed=351)[0]
     u = W.uniform_stream(n, seed=35000)
     v, _, _ = _check(B, herm, K, u, prec)
